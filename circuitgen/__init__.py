@@ -1,0 +1,123 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only draws inputs: random gate lists, the GHZ preparation list,
+Poisson request traces. It holds none of the simulator's arithmetic (no gate
+matrices, no error draws, no state updates), so both the FP64 oracle and the
+GPU library can be fed from it without sharing any of the method.
+
+The paper's own benchmark circuits (its Shor-factoring circuits, Table 2) are
+not printed in the paper, so random circuits over the paper's gate set
+(Section 2.0: one-, two- and three-bit controlled-NOTs plus rotation gates)
+stand in for them.
+
+Gate record layout (24 bytes, little endian), the interface both sides read:
+    uint32 kind, int32 target, int32 ctrl0, int32 ctrl1, float64 theta
+with ctrl = -1 when unused.  Qubit q is index bit 2**q of the state vector.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+H, RZ, X, CNOT, TOFFOLI, Z = 0, 1, 2, 3, 4, 5
+KIND_NAMES = {H: "H", RZ: "RZ", X: "X", CNOT: "CNOT", TOFFOLI: "TOFFOLI", Z: "Z"}
+ARITY = {H: 1, RZ: 1, X: 1, CNOT: 2, TOFFOLI: 3, Z: 1}
+
+GATE_DTYPE = np.dtype(
+    [("kind", "<u4"), ("target", "<i4"), ("ctrl0", "<i4"), ("ctrl1", "<i4"), ("theta", "<f8")],
+    align=False,
+)
+assert GATE_DTYPE.itemsize == 24
+
+
+def gates_from_list(items) -> np.ndarray:
+    """Build a gate array from tuples (kind, target, ctrl0=-1, ctrl1=-1, theta=0.0)."""
+    out = np.zeros(len(items), dtype=GATE_DTYPE)
+    for n, it in enumerate(items):
+        it = list(it)
+        kind, tgt = int(it[0]), int(it[1])
+        c0 = int(it[2]) if len(it) > 2 else -1
+        c1 = int(it[3]) if len(it) > 3 else -1
+        theta = float(it[4]) if len(it) > 4 else 0.0
+        out[n] = (kind, tgt, c0, c1, theta)
+    return out
+
+
+def random_circuit(num_qubits: int, num_gates: int, seed: int,
+                   kinds=(H, RZ, CNOT, TOFFOLI), top_bias: float = 0.0,
+                   top_count: int = 4) -> np.ndarray:
+    """Uniform random circuit over ``kinds`` on distinct random qubits.
+
+    Per gate: kind uniform over ``kinds``; qubits drawn without replacement,
+    the last one is the target and the rest are controls; RZ angle uniform on
+    [0, 2*pi).  With ``top_bias`` > 0 the target is, with that probability,
+    uniform over the top ``top_count`` qubits, otherwise uniform over all
+    qubits; controls are then uniform over the remaining qubits.
+    """
+    M = int(num_qubits)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.zeros(num_gates, dtype=GATE_DTYPE)
+    kinds = list(kinds)
+    for g in range(num_gates):
+        kind = kinds[int(rng.integers(len(kinds)))]
+        ar = ARITY[kind]
+        if ar > M:
+            raise ValueError(f"{KIND_NAMES[kind]} needs {ar} qubits, register has {M}")
+        if top_bias > 0.0:
+            if rng.random() < top_bias:
+                tgt = int(M - top_count + rng.integers(top_count))
+            else:
+                tgt = int(rng.integers(M))
+            rest = [q for q in range(M) if q != tgt]
+            ctrls = [int(c) for c in rng.choice(rest, ar - 1, replace=False)] if ar > 1 else []
+        else:
+            qs = [int(q) for q in rng.choice(M, ar, replace=False)]
+            tgt, ctrls = qs[-1], qs[:-1]
+        theta = float(rng.uniform(0.0, 2.0 * np.pi)) if kind == RZ else 0.0
+        c0 = ctrls[0] if len(ctrls) > 0 else -1
+        c1 = ctrls[1] if len(ctrls) > 1 else -1
+        out[g] = (kind, tgt, c0, c1, theta)
+    return out
+
+
+def ghz_circuit(num_qubits: int) -> np.ndarray:
+    """H on qubit 0, then CNOT(control q-1, target q) for q = 1..M-1."""
+    items = [(H, 0)] + [(CNOT, q, q - 1) for q in range(1, num_qubits)]
+    return gates_from_list(items)
+
+
+def save_gates(path, gates: np.ndarray) -> None:
+    np.ascontiguousarray(gates, dtype=GATE_DTYPE).tofile(path)
+
+
+def load_gates(path) -> np.ndarray:
+    return np.fromfile(path, dtype=GATE_DTYPE)
+
+
+def random_state(num_qubits: int, seed: int) -> np.ndarray:
+    """Random complex vector (not normalised), interleaved as float64 pairs."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal(2 * (1 << num_qubits))
+
+
+def poisson_trace(n_requests: int, rate_hz: float, seed: int,
+                  m_range=(10, 28), g_range=(100, 2000),
+                  sigmas=(1e-4, 1e-3, 1e-2)):
+    """Poisson request stream: arrival time, register size, gate count, sigma.
+
+    Returns a list of dicts with keys ``t`` (seconds from start), ``M``,
+    ``G``, ``sigma``, ``circuit_seed`` and ``error_seed``.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    reqs = []
+    for r in range(n_requests):
+        t += float(rng.exponential(1.0 / rate_hz)) if rate_hz > 0 else 0.0
+        reqs.append({
+            "t": t,
+            "M": int(rng.integers(m_range[0], m_range[1] + 1)),
+            "G": int(rng.integers(g_range[0], g_range[1] + 1)),
+            "sigma": float(sigmas[int(rng.integers(len(sigmas)))]),
+            "circuit_seed": int(seed) + r,
+            "error_seed": int(seed) + 1000 + r,
+        })
+    return reqs
