@@ -1,0 +1,246 @@
+/*
+ * qsim -- state-vector simulation with injected errors on one AMD Instinct
+ * MI355X (gfx950), after Obenland & Despain, "A Parallel Quantum Computer
+ * Simulator" (arXiv quant-ph/9804039).
+ *
+ * The library keeps one whole register of M qubits as a 2^M complex vector in
+ * device memory (Sec. 1.2 and Fig. 1: index bit q holds the value of qubit q),
+ * applies circuits of logic gates to it (Sec. 2.0: one-, two- and three-bit
+ * controlled-NOTs and rotations; Sec. 2.1: every gate is a 2x2 transform on
+ * the V/2 amplitude pairs that differ in the target bit), optionally injects
+ * errors at every step (Sec. 1.0, 1.4, 2.0: angle deviations; Sec. 3.4 and
+ * EQ 8: two extra decoherence transforms after every operation), and scores
+ * the result by an inner-product fidelity against another state.
+ *
+ * Conventions fixed by the library (the paper leaves them open):
+ *   - qubit q <-> index bit 2^q; on two qubits CNOT(control 1, target 0)
+ *     swaps amplitudes 2 and 3 (Table 1, Fig. 2);
+ *   - H = sqrt(1/2) [[1, 1], [1, -1]]; Rz(t) = diag(e^{-it/2}, e^{+it/2});
+ *   - angle error: one eps = sigma * z per gate, z ~ N(0, 1).  Rz(t) becomes
+ *     Rz(t + eps); H, X, CNOT, Toffoli and Z become i * R_n(pi + eps) about
+ *     their own axis n (so eps = 0 gives the textbook gate exactly, and the
+ *     unperturbed X/CNOT/Toffoli/Z are exact amplitude swaps / sign flips);
+ *   - decoherence after every gate: for q = 0..M-1 in turn, a bit flip X_q
+ *     with probability p_bitflip, then a phase flip Z_q with probability
+ *     p_phaseflip, both exact;
+ *   - draws: Philox4x64-10 (Salmon et al., SC'11), key (seed, trial),
+ *     counter (step, qubit, stream, 0).  The angle of a step uses counter
+ *     (step, 0, 1, 0) and Box-Muller on the high 32 bits of output words 0
+ *     and 1, u = (h + 0.5) 2^-32.  The flips of qubit q use counter
+ *     (step, q, 2, 0): word 0 decides the bit flip, word 1 the phase flip;
+ *     each fires when its high 32 bits are below floor(p 2^32);
+ *   - step = number of circuit gates applied to the state since create or
+ *     reset; flips and inverse (echo) gates do not count.
+ *
+ * Threading: one state must not be used from two host threads at once.
+ * Different states may be used concurrently.  Error messages are per thread.
+ *
+ * Return values: QSIM_OK (0) or a negative status.  On QSIM_EINVAL nothing
+ * has been written or launched.  No function aborts or throws.
+ */
+#ifndef QSIM_INCLUDE_QSIM_API_H_
+#define QSIM_INCLUDE_QSIM_API_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QSIM_OK 0
+#define QSIM_EINVAL (-1)   /* invalid argument: qubit, arity, sizes, dtype */
+#define QSIM_ENOMEM (-2)   /* device or pinned host memory does not fit */
+#define QSIM_EDEVICE (-3)  /* a HIP runtime call failed */
+#define QSIM_ERANGE (-4)   /* index range out of bounds */
+
+#define QSIM_MAX_QUBITS 34
+
+typedef struct qsim_state qsim_state; /* opaque, owned by the library */
+
+typedef enum { QSIM_C64 = 0, QSIM_C128 = 1 } qsim_dtype;
+
+/* Gate kinds.  Arity: H, RZ, X, Z act on `target` alone; CNOT adds ctrl0;
+ * TOFFOLI adds ctrl0 and ctrl1.  Unused controls are -1. */
+typedef enum {
+    QSIM_H = 0,
+    QSIM_RZ = 1,
+    QSIM_X = 2,
+    QSIM_CNOT = 3,
+    QSIM_TOFFOLI = 4,
+    QSIM_Z = 5
+} qsim_kind;
+
+/* One gate, 24 bytes.  theta is the Rz angle in radians (ignored otherwise). */
+typedef struct {
+    uint32_t kind;
+    int32_t target;
+    int32_t ctrl0;
+    int32_t ctrl1;
+    double theta;
+} qsim_gate;
+
+/* Error model (Sec. 1.4, 2.0, 3.4).  sigma >= 0 radians; p in [0, 1]. */
+typedef struct {
+    double sigma;
+    double p_bitflip;
+    double p_phaseflip;
+    uint64_t seed;
+    uint64_t trial;
+} qsim_error_model;
+
+/* Creation options; a zeroed struct (or NULL) gives the defaults. */
+typedef struct {
+    int device;          /* HIP device ordinal (default 0) */
+    void *hip_stream;    /* hipStream_t the state's work goes to; NULL: the
+                            library creates one at default priority */
+    void *ext_buffer;    /* device memory that holds the state, borrowed (never
+                            freed by the library); NULL: the library allocates */
+    size_t ext_bytes;    /* size of ext_buffer, >= 2^M * element size */
+    int renorm_period;   /* rescale to unit norm after every R gates.
+                            0: default (64 for QSIM_C64, never for QSIM_C128);
+                            -1: never */
+    int exec_mode;       /* 0: fused passes (default); 1: one pass per gate */
+    int tile_bits;       /* qubits per fused tile, 9..14; 0: default (13 for
+                            QSIM_C64, 12 for QSIM_C128) */
+    int low_bits;        /* low qubits always in a fused tile, 1..tile_bits-1;
+                            0: default (5) */
+    int group_bits;      /* qubits per register quantum, 3..5, with
+                            6 <= tile_bits - group_bits <= 9; 0: default (5 for
+                            QSIM_C64, 4 for QSIM_C128) */
+} qsim_options;
+
+/* Per-state counters of the work launched since the last reset of the
+ * counters (qsim_profile).  Times come from HIP events around each launch and
+ * are only filled while profiling is on. */
+typedef struct {
+    uint64_t gates;          /* circuit gates applied */
+    uint64_t flips;          /* injected flips applied */
+    uint64_t passes;         /* state-update kernel launches (plain + fused) */
+    uint64_t fused_passes;   /* of which fused tile passes */
+    uint64_t renorms;        /* renormalisations */
+    double pass_ms;          /* summed duration of the state-update launches */
+    double pass_bytes;       /* algorithmic HBM bytes of those launches */
+    double fused_ms;         /* summed duration of the fused launches */
+    double fused_bytes;      /* algorithmic HBM bytes of the fused launches */
+    double other_ms;         /* reductions, init, scaling */
+} qsim_stats;
+
+/* Allocate a register of num_qubits (1..QSIM_MAX_QUBITS) in `dtype` and set it
+ * to |0...0> (Fig. 1(a)).  Errors start disarmed.  EINVAL for bad arguments,
+ * ENOMEM if 2^M elements do not fit (or ext_bytes is too small: EINVAL). */
+int qsim_create(int num_qubits, int dtype, const qsim_options *opt, qsim_state **out);
+
+/* Wait for the state's work, release its memory (unless borrowed) and its
+ * stream (unless borrowed).  NULL is accepted. */
+int qsim_destroy(qsim_state *s);
+
+/* Set the state to the basis state |basis_index> and the step counter to 0.
+ * ERANGE if basis_index >= 2^M. */
+int qsim_reset(qsim_state *s, uint64_t basis_index);
+
+/* Apply gates[0..n_gates) in order (Sec. 2.1), each followed by the armed
+ * error model's draws for its step.  Asynchronous on the state's stream; the
+ * gate array is read before returning.  EINVAL (nothing applied) if any gate
+ * has a bad kind, arity, qubit, repeated qubit or a non-finite theta. */
+int qsim_apply_circuit(qsim_state *s, const qsim_gate *gates, size_t n_gates);
+
+/* Apply the exact inverse of gates[0..n_gates): the gates in reverse order,
+ * Rz(t) as Rz(-t), the others as themselves, with no errors and without
+ * advancing the step counter.  After a noisy run of a circuit, this leaves
+ * <0|U_ideal^dagger U_noisy|0> in amplitude 0 (the echo form of the fidelity,
+ * for registers too large to hold two states). */
+int qsim_apply_inverse(qsim_state *s, const qsim_gate *gates, size_t n_gates);
+
+/* Arm the error model for later apply_circuit calls (copied), or disarm it
+ * with NULL.  With sigma = 0 and both p = 0 the run is bit-identical to a run
+ * with errors disarmed.  EINVAL for negative/non-finite sigma or p outside
+ * [0, 1]. */
+int qsim_inject_errors(qsim_state *s, const qsim_error_model *em);
+
+/* F = |<a|b>|^2 / (<a|a> <b|b>), accumulated in FP64 on the device with a
+ * fixed reduction order (deterministic).  a and b must have the same M; their
+ * dtypes may differ.  Synchronises both states' streams. */
+int qsim_fidelity(const qsim_state *a, const qsim_state *b, double *out_F);
+
+/* out = {re <a|b>, im <a|b>, <a|a>, <b|b>} in FP64 (same rules as above). */
+int qsim_overlap(const qsim_state *a, const qsim_state *b, double out[4]);
+
+/* Squared norm <s|s> in FP64. */
+int qsim_norm(const qsim_state *s, double *out);
+
+/* Probabilities |a_i|^2 (Sec. 1.2) in FP64 into host memory `out`.  With
+ * qubit_mask covering m qubits, out_len must be 2^m; out[k] sums every index
+ * whose masked bits, in ascending qubit order, spell k.  qubit_mask = 2^M - 1
+ * gives the full distribution.  EINVAL for mask bits >= M or a wrong
+ * out_len. */
+int qsim_probs(const qsim_state *s, uint64_t qubit_mask, double *out, size_t out_len);
+
+/* Copy amplitudes [offset, offset + count) to host memory as interleaved
+ * FP64 re/im pairs (2 * count doubles).  ERANGE if out of bounds. */
+int qsim_get_amplitudes(const qsim_state *s, uint64_t offset, uint64_t count, double *out);
+
+/* Overwrite amplitudes [offset, offset + count) from interleaved FP64 host
+ * memory (rounded to the state's dtype).  Does not touch the step counter. */
+int qsim_set_amplitudes(qsim_state *s, uint64_t offset, uint64_t count, const double *in);
+
+/* Batched Monte Carlo: the error-free run of gates[0..n) from |0...0> is the
+ * reference; trial t (0 <= t < n_trials) runs the same circuit from |0...0>
+ * with error model `base` keyed by trial base->trial + t, and out_F[t] is its
+ * fidelity against the reference (host memory, n_trials doubles).  All trials
+ * run in one persistent launch, one register per workgroup, which needs the
+ * register to fit the workgroup's LDS (num_qubits <= 14 for QSIM_C64,
+ * <= 13 for QSIM_C128); EINVAL beyond that.  Synchronous.  Runs on `device`
+ * 0 unless QSIM_DEVICE is set in the environment. */
+int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits, int dtype,
+                    const qsim_error_model *base, uint64_t n_trials, double *out_F);
+
+/* One pass of a fused schedule (qsim_plan). */
+typedef struct {
+    uint32_t fused;      /* 1: tile pass (one HBM read + write for all its
+                            operations); 0: one whole-vector pass per operation */
+    uint32_t first_op;   /* index into the lowered operation stream (gates plus
+                            injected flips, in order) */
+    uint32_t n_ops;
+    uint32_t n_groups;   /* register groups inside a tile pass */
+    uint32_t norm_after; /* 1: a renormalisation follows this pass */
+    uint32_t pad;
+    uint64_t tile_mask;  /* qubits spanned by the tile of a fused pass */
+} qsim_pass_info;
+
+/* Host-only dry run of qsim_apply_circuit for a register created with
+ * (num_qubits, dtype, opt): lower the gates (drawing the errors of em, NULL =
+ * none, starting at step0), partition the operation stream into passes the
+ * way the library would (Sec. 2.1: a gate only mixes the amplitude pairs of
+ * its target, so a run of gates whose targets lie in one set of qubits can
+ * be applied tile by tile in one pass over the state), and check every pass's
+ * kernel arguments for consistency.  Writes min(out_cap, passes) entries of
+ * out (may be NULL), and the pass and operation counts.  No device is used.
+ * EINVAL for bad arguments; EDEVICE if a pass fails its own consistency
+ * check (a library bug). */
+int qsim_plan(int num_qubits, int dtype, const qsim_options *opt, const qsim_gate *gates,
+              size_t n_gates, const qsim_error_model *em, uint64_t step0, qsim_pass_info *out,
+              size_t out_cap, size_t *n_passes, size_t *n_ops);
+
+/* Wait for all work queued on the state's stream. */
+int qsim_synchronize(qsim_state *s);
+
+/* Register size, dtype, step counter, device pointer and byte size. */
+int qsim_info(const qsim_state *s, int *num_qubits, int *dtype, uint64_t *step,
+              void **device_ptr, size_t *bytes);
+
+/* Turn per-launch HIP event timing on (1) or off (0); either way the
+ * counters are zeroed. */
+int qsim_profile(qsim_state *s, int enable);
+
+/* Read the counters (synchronises the stream when profiling is on). */
+int qsim_get_stats(qsim_state *s, qsim_stats *out);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *qsim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSIM_INCLUDE_QSIM_API_H_ */

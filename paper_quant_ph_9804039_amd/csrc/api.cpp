@@ -1,0 +1,1265 @@
+// C-ABI of the qsim library: state management, gate lowering with error
+// injection, the pass scheduler, and the FP64 readouts.  All device work goes
+// to the state's HIP stream; nothing here computes amplitudes on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "launch.h"
+#include "qsim.h"
+
+using namespace qsim;
+
+// ------------------------------------------------------------------ errors
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory)
+        return fail(QSIM_ENOMEM, "%s: out of device memory", what);
+    return fail(QSIM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                     \
+    do {                                        \
+        hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess)                   \
+            return hip_fail(e_, what);          \
+    } while (0)
+
+struct PendingTiming {
+    hipEvent_t start, stop;
+    int kind;      // 0 plain pass, 1 fused pass, 2 other
+    double bytes;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------- state
+
+struct qsim_state {
+    int M = 0;
+    int dtype = QSIM_C64;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void *psi = nullptr;
+    size_t bytes = 0;
+    bool own_mem = false;
+    uint64_t step = 0;
+    bool armed = false;
+    qsim_error_model em{};
+    int renorm_period = 0;   // 0 = never
+    int exec_mode = 0;
+    int tile_bits = 13;
+    int low_bits = 5;
+    int group_bits = 5;
+    double *d_partial = nullptr;   // reduction partials
+    size_t partial_len = 0;
+    double *d_tile_norm = nullptr; // per-tile norms of a fused pass
+    double *d_scalars = nullptr;   // [0..3] overlap / norm, [4] norm sum, [5] scale
+    double *h_pinned = nullptr;    // 16 doubles
+    void *d_stage = nullptr;
+    size_t stage_bytes = 0;
+    bool profiling = false;
+    qsim_stats stats{};
+    std::vector<PendingTiming> pending;
+    std::vector<hipEvent_t> free_events;
+};
+
+namespace {
+
+size_t elem_bytes(int dtype) { return dtype == QSIM_C64 ? 8 : 16; }
+
+int env_int(const char *name, int dflt)
+{
+    const char *v = getenv(name);
+    if (v == nullptr || *v == 0)
+        return dflt;
+    return atoi(v);
+}
+
+// ------------------------------------------------------------ profiling
+
+hipEvent_t take_event(qsim_state *s)
+{
+    if (!s->free_events.empty()) {
+        hipEvent_t e = s->free_events.back();
+        s->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+int flush_timings(qsim_state *s)
+{
+    if (s->pending.empty())
+        return QSIM_OK;
+    HIP_TRY(hipStreamSynchronize(s->stream), "timing sync");
+    for (const PendingTiming &p : s->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+            if (p.kind == 0 || p.kind == 1) {
+                s->stats.pass_ms += ms;
+                s->stats.pass_bytes += p.bytes;
+            }
+            if (p.kind == 1) {
+                s->stats.fused_ms += ms;
+                s->stats.fused_bytes += p.bytes;
+            }
+            if (p.kind == 2)
+                s->stats.other_ms += ms;
+        }
+        s->free_events.push_back(p.start);
+        s->free_events.push_back(p.stop);
+    }
+    s->pending.clear();
+    return QSIM_OK;
+}
+
+// Wraps one launch with events when profiling.
+struct Timed {
+    qsim_state *s;
+    hipEvent_t a = nullptr;
+    int kind;
+    double bytes;
+    Timed(qsim_state *st, int kd, double by) : s(st), kind(kd), bytes(by)
+    {
+        if (s->profiling) {
+            a = take_event(s);
+            if (a)
+                (void)hipEventRecord(a, s->stream);
+        }
+    }
+    void done()
+    {
+        if (!s->profiling || a == nullptr)
+            return;
+        hipEvent_t b = take_event(s);
+        if (b == nullptr)
+            return;
+        (void)hipEventRecord(b, s->stream);
+        s->pending.push_back({a, b, kind, bytes});
+        if (s->pending.size() > 8192)
+            flush_timings(s);
+    }
+};
+
+// ---------------------------------------------------------------- lowering
+
+constexpr size_t kMaxLdsBytes = 160 * 1024;  // gfx950 LDS per workgroup
+
+constexpr double kSqrtHalf = 0.70710678118654752440084436210485;
+
+bool gate_ok(const qsim_gate &g, int M, char *why, size_t n)
+{
+    int need;
+    switch (g.kind) {
+    case QSIM_H: case QSIM_RZ: case QSIM_X: case QSIM_Z: need = 0; break;
+    case QSIM_CNOT: need = 1; break;
+    case QSIM_TOFFOLI: need = 2; break;
+    default: snprintf(why, n, "unknown gate kind %u", g.kind); return false;
+    }
+    if (g.target < 0 || g.target >= M) {
+        snprintf(why, n, "target %d outside [0, %d)", g.target, M);
+        return false;
+    }
+    const int c[2] = {g.ctrl0, g.ctrl1};
+    for (int i = 0; i < 2; ++i) {
+        const bool used = i < need;
+        if (!used && c[i] != -1) {
+            snprintf(why, n, "gate kind %u takes %d control(s)", g.kind, need);
+            return false;
+        }
+        if (used && (c[i] < 0 || c[i] >= M)) {
+            snprintf(why, n, "control %d outside [0, %d)", c[i], M);
+            return false;
+        }
+        if (used && c[i] == g.target) {
+            snprintf(why, n, "control %d equals the target", c[i]);
+            return false;
+        }
+    }
+    if (need == 2 && g.ctrl0 == g.ctrl1) {
+        snprintf(why, n, "repeated control %d", g.ctrl0);
+        return false;
+    }
+    if (!std::isfinite(g.theta)) {
+        snprintf(why, n, "non-finite theta");
+        return false;
+    }
+    return true;
+}
+
+// The 2x2 of a gate with angle error eps (FP64).  eps == 0 gives the textbook
+// gate; otherwise the gate is i R_n(pi + eps) about its own axis n, and Rz(t)
+// is Rz(t + eps).
+Op lower_gate(const qsim_gate &g, double eps, bool inverse)
+{
+    Op op{};
+    op.target = g.target;
+    op.cmask = 0;
+    if (g.ctrl0 >= 0)
+        op.cmask |= 1ull << g.ctrl0;
+    if (g.ctrl1 >= 0)
+        op.cmask |= 1ull << g.ctrl1;
+    const double c = std::cos(0.5 * eps), sn = std::sin(0.5 * eps);
+    auto set = [&](int idx, double re, double im) {
+        op.u[2 * idx] = re;
+        op.u[2 * idx + 1] = im;
+    };
+    switch (g.kind) {
+    case QSIM_H: {
+        op.type = kOpMat;
+        if (eps == 0.0) {
+            set(0, kSqrtHalf, 0); set(1, kSqrtHalf, 0); set(2, kSqrtHalf, 0); set(3, -kSqrtHalf, 0);
+        } else {
+            const double ch = c * kSqrtHalf;
+            set(0, ch, -sn); set(1, ch, 0); set(2, ch, 0); set(3, -ch, -sn);
+        }
+        break;
+    }
+    case QSIM_RZ: {
+        op.type = kOpDiag;
+        const double phi = (inverse ? -g.theta : g.theta) + eps;
+        const double cp = std::cos(0.5 * phi), sp = std::sin(0.5 * phi);
+        set(0, cp, -sp); set(3, cp, sp);
+        break;
+    }
+    case QSIM_X: case QSIM_CNOT: case QSIM_TOFFOLI:
+        if (eps == 0.0) {
+            op.type = kOpSwap;
+            set(1, 1, 0); set(2, 1, 0);
+        } else {
+            op.type = kOpMat;
+            set(0, 0, -sn); set(1, c, 0); set(2, c, 0); set(3, 0, -sn);
+        }
+        break;
+    default:  // QSIM_Z
+        if (eps == 0.0) {
+            op.type = kOpNeg;
+            set(0, 1, 0); set(3, -1, 0);
+        } else {
+            op.type = kOpDiag;
+            set(0, c, -sn); set(3, -c, -sn);
+        }
+        break;
+    }
+    return op;
+}
+
+// Gates plus the armed error model's draws -> operations (Sec. 2.0: angle
+// deviation per gate; Sec. 3.4: two extra transforms after every operation).
+void lower_circuit(const qsim_state *s, const qsim_gate *gates, size_t n, std::vector<Op> &ops)
+{
+    const bool ang = s->armed && s->em.sigma > 0.0;
+    const bool flips = s->armed && (s->em.p_bitflip > 0.0 || s->em.p_phaseflip > 0.0);
+    const uint64_t thr_b = flips ? flip_threshold(s->em.p_bitflip) : 0;
+    const uint64_t thr_p = flips ? flip_threshold(s->em.p_phaseflip) : 0;
+    ops.reserve(ops.size() + n);
+    for (size_t k = 0; k < n; ++k) {
+        const uint64_t step = s->step + k;
+        const double eps = ang ? s->em.sigma * step_gaussian(s->em.seed, s->em.trial, step) : 0.0;
+        Op op = lower_gate(gates[k], eps, false);
+        op.step = step;
+        op.is_flip = false;
+        op.step_end = true;
+        ops.push_back(op);
+        if (!flips)
+            continue;
+        for (int q = 0; q < s->M; ++q) {
+            const u64x4 r = philox4x64_10(step, (uint64_t)q, kStreamFlip, 0, s->em.seed, s->em.trial);
+            const bool bf = (r.w[0] >> 32) < thr_b;
+            const bool pf = (r.w[1] >> 32) < thr_p;
+            if (!bf && !pf)
+                continue;
+            ops.back().step_end = false;
+            if (bf) {
+                Op x{};
+                x.type = kOpSwap;
+                x.target = q;
+                x.u[2] = 1; x.u[4] = 1;
+                x.step = step;
+                x.is_flip = true;
+                x.step_end = true;
+                ops.push_back(x);
+            }
+            if (pf) {
+                if (bf)
+                    ops.back().step_end = false;
+                Op z{};
+                z.type = kOpNeg;
+                z.target = q;
+                z.u[0] = 1; z.u[6] = -1;
+                z.step = step;
+                z.is_flip = true;
+                z.step_end = true;
+                ops.push_back(z);
+            }
+        }
+    }
+}
+
+// Algorithmic HBM bytes of one operation done as its own pass.
+double plain_bytes(const qsim_state *s, const Op &op)
+{
+    const double full = 2.0 * (double)(1ull << s->M) * (double)elem_bytes(s->dtype);
+    const int nc = __builtin_popcountll(op.cmask);
+    double frac = 1.0 / (double)(1ull << nc);
+    if (op.type == kOpNeg)
+        frac *= 0.5;
+    return full * frac;
+}
+
+// ------------------------------------------------------------- scheduling
+
+struct PassPlan {
+    bool fused;
+    size_t first, count;
+    bool norm_after;   // compute the norm after this pass (renorm boundary)
+};
+
+// Operations whose target must be a tile qubit of a fused pass (and a group
+// bit inside it): everything but uncontrolled diagonals.
+bool needs_tile_target(const Op &op)
+{
+    return op.type == kOpMat || op.type == kOpSwap || op.cmask != 0;
+}
+
+// Operations a fused pass can carry: everything but a 2x2 with complex
+// off-diagonal entries (no gate of the set lowers to one; such an operation
+// gets a pass of its own).
+bool fusable(const Op &op)
+{
+    return !(op.type == kOpMat && (op.u[3] != 0.0 || op.u[5] != 0.0));
+}
+
+bool renorm_due(const qsim_state *s, const Op &op)
+{
+    return s->renorm_period > 0 && op.step_end && ((op.step + 1) % (uint64_t)s->renorm_period) == 0;
+}
+
+// Shape of the fused passes of a state: k tile qubits, G group bits per
+// register quantum, 2^(k-G) threads per workgroup with 6 <= k - G <= 9.
+// False when the register is too small for a fused pass (M < 9).
+bool tile_shape(const qsim_state *s, int &k, int &G)
+{
+    k = std::min(s->tile_bits, s->M);
+    G = std::min(std::max(s->group_bits, k - 9), k - 6);
+    return G >= 3 && G <= 5;
+}
+
+// Greedy, order-preserving partition into passes.  A fused pass starts with
+// the low qubits in its tile set and adds the target of each next
+// non-diagonal operation until the set holds k qubits; diagonal operations
+// never constrain it.  A pass also ends at a renormalisation boundary.
+void schedule(const qsim_state *s, const std::vector<Op> &ops, std::vector<PassPlan> &plan)
+{
+    const size_t n = ops.size();
+    int k, G;
+    if (s->exec_mode == 1 || !tile_shape(s, k, G)) {
+        for (size_t i = 0; i < n; ++i)
+            plan.push_back({false, i, 1, renorm_due(s, ops[i])});
+        return;
+    }
+    const int low = std::min(s->low_bits, k);
+    size_t i = 0;
+    while (i < n) {
+        uint64_t S = (low >= 64) ? ~0ull : ((1ull << low) - 1);
+        int size = low;
+        size_t j = i;
+        bool norm = false;
+        while (j < n && j - i < (size_t)kMaxPassOps) {
+            const Op &op = ops[j];
+            if (!fusable(op))
+                break;
+            if (needs_tile_target(op)) {
+                const uint64_t tb = 1ull << op.target;
+                if (!(S & tb)) {
+                    if (size == k)
+                        break;
+                    S |= tb;
+                    ++size;
+                }
+            }
+            ++j;
+            if (renorm_due(s, op)) {
+                norm = true;
+                break;
+            }
+        }
+        if (j == i) {
+            // the tile cannot take this target (no free tile qubit): own pass
+            plan.push_back({false, i, 1, renorm_due(s, ops[i])});
+            i = i + 1;
+            continue;
+        }
+        plan.push_back({true, i, j - i, norm});
+        i = j;
+    }
+}
+
+// Build the kernel arguments of one fused pass.
+template <typename R>
+void build_tile_args(const qsim_state *s, const std::vector<Op> &ops, const PassPlan &p,
+                     TileArgs<R> &A, int &G)
+{
+    const int M = s->M;
+    int k;
+    tile_shape(s, k, G);
+    const int low = std::min(s->low_bits, k);
+    // tile qubit set: low qubits, then the pass's targets, then the lowest free qubits
+    uint64_t S = (1ull << low) - 1;
+    for (size_t o = p.first; o < p.first + p.count; ++o)
+        if (needs_tile_target(ops[o]))
+            S |= 1ull << ops[o].target;
+    for (int q = 0; q < M && __builtin_popcountll(S) < k; ++q)
+        S |= 1ull << q;
+    std::memset(&A, 0, sizeof(A));
+    A.M = (uint32_t)M;
+    A.k = (uint32_t)k;
+    A.low = (uint32_t)low;
+    A.smask = S;
+    int tpos_of[64];
+    int m = 0;
+    for (int q = 0; q < M; ++q) {
+        if (S & (1ull << q)) {
+            A.spos[m] = (uint8_t)q;
+            tpos_of[q] = m++;
+        } else {
+            tpos_of[q] = -1;
+        }
+    }
+    // runs of consecutive qubits of S and of its complement, ascending
+    for (int q = 0; q < M;) {
+        const bool in = (S >> q) & 1u;
+        int e = q;
+        while (e < M && (((S >> e) & 1u) != 0) == in)
+            ++e;
+        uint32_t &n = in ? A.nsrun : A.ncrun;
+        (in ? A.srun : A.crun)[n] = (uint32_t)q | ((uint32_t)(e - q) << 8);
+        ++n;
+        q = e;
+    }
+    // operations, grouped so that the targets that need a group bit span at
+    // most G tile bits per group
+    A.nops = (uint32_t)p.count;
+    std::vector<uint32_t> cur;  // tile bits of the current group
+    uint32_t gfirst = 0;
+    std::vector<std::pair<uint32_t, std::vector<uint32_t>>> groups;  // (first | count, bits)
+    auto close_group = [&](uint32_t end) {
+        if (end == gfirst)
+            return;
+        groups.push_back({gfirst | ((end - gfirst) << kGroupCountShift), cur});
+        cur.clear();
+        gfirst = end;
+    };
+    for (uint32_t o = 0; o < A.nops; ++o) {
+        const Op &op = ops[p.first + o];
+        if (needs_tile_target(op)) {
+            const uint32_t tp = (uint32_t)tpos_of[op.target];
+            if (std::find(cur.begin(), cur.end(), tp) == cur.end()) {
+                if ((int)cur.size() == G)
+                    close_group(o);
+                cur.push_back(tp);
+            }
+        }
+    }
+    close_group(A.nops);
+    A.ngroups = (uint32_t)groups.size();
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        std::vector<uint32_t> bits = groups[gi].second;
+        // pad with the highest free tile bits (keeps tile bit 0 outside the
+        // group, so neighbouring threads touch neighbouring LDS words)
+        for (int b = k - 1; b >= 0 && (int)bits.size() < G; --b)
+            if (std::find(bits.begin(), bits.end(), (uint32_t)b) == bits.end())
+                bits.push_back((uint32_t)b);
+        std::sort(bits.begin(), bits.end());
+        uint32_t w = groups[gi].first;
+        for (int i = 0; i < G; ++i)
+            w |= bits[i] << (kGroupBitsShift + 4 * i);
+        A.group[gi] = w;
+        auto gidx = [&](int q) -> int {
+            if (tpos_of[q] < 0)
+                return -1;
+            const auto it = std::find(bits.begin(), bits.end(), (uint32_t)tpos_of[q]);
+            return it == bits.end() ? -1 : (int)(it - bits.begin());
+        };
+        const uint32_t first = group_first(w), cnt = group_count(w);
+        for (uint32_t o = first; o < first + cnt && o < A.nops; ++o) {
+            const Op &op = ops[p.first + o];
+            TileOp<R> &t = A.ops[o];
+            std::memset(&t, 0, sizeof(t));
+            t.tq = (uint32_t)op.target;
+            t.tpos = tpos_of[op.target] >= 0 ? (uint32_t)tpos_of[op.target] : kNoPos;
+            const int gp = gidx(op.target);
+            t.gpos = gp >= 0 ? (uint8_t)gp : (uint8_t)0;
+            for (int q = 0; q < M; ++q) {
+                if (!(op.cmask & (1ull << q)))
+                    continue;
+                const int cg = gidx(q);
+                if (tpos_of[q] < 0)
+                    t.cm_out |= 1ull << q;
+                else if (cg >= 0)
+                    t.rc |= (uint8_t)(1u << cg);
+                else
+                    t.qc |= 1u << tpos_of[q];
+            }
+            const double *u = op.u;
+            switch (op.type) {
+            case kOpMat:
+                // real off-diagonal (fusable() admits no other matrix): real
+                // 2x2 plus i*w on the diagonal
+                t.kind = kTPair;
+                t.c[0] = (R)u[0]; t.c[1] = (R)u[2]; t.c[2] = (R)u[4]; t.c[3] = (R)u[6];
+                t.c[4] = (R)u[1]; t.c[5] = (R)u[7];
+                t.has_w = (u[1] != 0.0 || u[7] != 0.0) ? 1 : 0;
+                break;
+            case kOpSwap:
+                t.kind = kTSwap;
+                break;
+            case kOpDiag:
+                t.kind = gp >= 0 ? kTDiagIn : kTDiagOut;
+                t.c[0] = (R)u[0]; t.c[1] = (R)u[1]; t.c[2] = (R)u[6]; t.c[3] = (R)u[7];
+                break;
+            default:
+                t.kind = gp >= 0 ? kTNegIn : kTNegOut;
+                break;
+            }
+        }
+    }
+}
+
+// Internal consistency of a fused pass's arguments (used by qsim_plan).
+template <typename R>
+bool tile_args_consistent(const TileArgs<R> &A, int G, const std::vector<Op> &ops,
+                          const PassPlan &p, char *why, size_t n)
+{
+    if (A.nops != p.count || A.nops == 0 || A.nops > (uint32_t)kMaxPassOps) {
+        snprintf(why, n, "op count %u", A.nops);
+        return false;
+    }
+    if (A.ngroups == 0 || A.ngroups > (uint32_t)kMaxGroups) {
+        snprintf(why, n, "group count %u", A.ngroups);
+        return false;
+    }
+    if ((uint64_t)__builtin_popcountll(A.smask) != A.k || A.k - (uint32_t)G < 6 || A.k - (uint32_t)G > 9) {
+        snprintf(why, n, "tile set / shape");
+        return false;
+    }
+    // the run tables must spell the tile set and its complement, in order
+    uint64_t sm = 0, cm = 0;
+    uint32_t sl = 0, cl = 0;
+    for (uint32_t i = 0; i < A.nsrun && i < (uint32_t)kMaxRuns; ++i) {
+        sm |= ((1ull << (A.srun[i] >> 8)) - 1) << (A.srun[i] & 0xFFu);
+        sl += A.srun[i] >> 8;
+        if (i > 0 && (A.srun[i] & 0xFFu) <= (A.srun[i - 1] & 0xFFu))
+            sm = 0;
+    }
+    for (uint32_t i = 0; i < A.ncrun && i < (uint32_t)kMaxRuns; ++i) {
+        cm |= ((1ull << (A.crun[i] >> 8)) - 1) << (A.crun[i] & 0xFFu);
+        cl += A.crun[i] >> 8;
+        if (i > 0 && (A.crun[i] & 0xFFu) <= (A.crun[i - 1] & 0xFFu))
+            cm = 0;
+    }
+    const uint64_t full = (A.M >= 64) ? ~0ull : ((1ull << A.M) - 1);
+    if (A.nsrun > (uint32_t)kMaxRuns || A.ncrun > (uint32_t)kMaxRuns || sm != A.smask ||
+        cm != (full & ~A.smask) || sl != A.k || cl != A.M - A.k) {
+        snprintf(why, n, "run tables");
+        return false;
+    }
+    uint32_t next = 0;
+    for (uint32_t gi = 0; gi < A.ngroups; ++gi) {
+        const uint32_t w = A.group[gi];
+        if (group_first(w) != next || group_count(w) == 0) {
+            snprintf(why, n, "group %u does not continue at op %u", gi, next);
+            return false;
+        }
+        next += group_count(w);
+        uint32_t seen = 0;
+        for (int i = 0; i < G; ++i) {
+            const uint32_t b = group_bit(w, i);
+            if (b >= A.k || (seen >> b) & 1u || (i > 0 && b <= group_bit(w, i - 1))) {
+                snprintf(why, n, "group %u bits", gi);
+                return false;
+            }
+            seen |= 1u << b;
+        }
+        for (uint32_t o = group_first(w); o < next; ++o) {
+            const Op &op = ops[p.first + o];
+            const TileOp<R> &t = A.ops[o];
+            const bool in_tile = (A.smask >> op.target) & 1u;
+            if (t.kind <= kTNegIn) {
+                if (!in_tile || t.gpos >= (uint32_t)G || group_bit(w, t.gpos) != t.tpos) {
+                    snprintf(why, n, "op %u target not on its group bit", o);
+                    return false;
+                }
+            } else if (op.cmask != 0) {
+                snprintf(why, n, "op %u: controlled diagonal folded", o);
+                return false;
+            }
+            // the three control masks must rebuild the op's control set
+            uint64_t back = t.cm_out;
+            for (int i = 0; i < G; ++i)
+                if ((t.rc >> i) & 1u)
+                    back |= 1ull << A.spos[group_bit(w, i)];
+            for (uint32_t m = 0; m < A.k; ++m)
+                if ((t.qc >> m) & 1u)
+                    back |= 1ull << A.spos[m];
+            if (back != op.cmask) {
+                snprintf(why, n, "op %u control masks", o);
+                return false;
+            }
+        }
+    }
+    if (next != A.nops) {
+        snprintf(why, n, "groups cover %u of %u ops", next, A.nops);
+        return false;
+    }
+    return true;
+}
+
+template <typename R>
+int run_ops(qsim_state *s, const std::vector<Op> &ops)
+{
+    std::vector<PassPlan> plan;
+    schedule(s, ops, plan);
+    cplx<R> *psi = reinterpret_cast<cplx<R> *>(s->psi);
+    const double full = 2.0 * (double)(1ull << s->M) * (double)elem_bytes(s->dtype);
+    bool scale_pending = false;
+    double *norm_sum = s->d_scalars + 4;   // [4] = sum, [5] = 1/sqrt(sum)
+    for (const PassPlan &p : plan) {
+        if (p.fused) {
+            TileArgs<R> A;
+            int G = 0;
+            build_tile_args<R>(s, ops, p, A, G);
+            A.psi = psi;
+            A.scale_in = scale_pending ? norm_sum + 1 : nullptr;
+            A.norm_out = p.norm_after ? s->d_tile_norm : nullptr;
+            Timed t(s, 1, full);
+            HIP_TRY(launch_tile<R>(A, G, s->stream), "fused pass launch");
+            t.done();
+            scale_pending = false;
+            s->stats.fused_passes++;
+            if (p.norm_after) {
+                Timed t2(s, 2, 0);
+                HIP_TRY(launch_finish_norm(s->d_tile_norm, 1ull << (s->M - A.k), norm_sum,
+                                           s->stream), "norm launch");
+                t2.done();
+                scale_pending = true;
+                s->stats.renorms++;
+            }
+        } else {
+            if (scale_pending) {
+                Timed t0(s, 2, full);
+                HIP_TRY(launch_scale<R>(psi, s->M, norm_sum + 1, s->stream), "scale launch");
+                t0.done();
+                scale_pending = false;
+            }
+            const Op &op = ops[p.first];
+            Timed t(s, 0, plain_bytes(s, op));
+            HIP_TRY(launch_plain<R>(op, psi, s->M, s->stream), "pass launch");
+            t.done();
+            if (p.norm_after) {
+                Timed t2(s, 2, full / 2);
+                HIP_TRY(launch_norm<R>(psi, s->M, s->d_partial, s->d_scalars, s->stream), "norm");
+                HIP_TRY(launch_finish_norm(s->d_scalars + 2, 1, norm_sum, s->stream), "norm");
+                t2.done();
+                scale_pending = true;
+                s->stats.renorms++;
+            }
+        }
+        s->stats.passes++;
+    }
+    if (scale_pending) {
+        Timed t0(s, 2, full);
+        HIP_TRY(launch_scale<R>(psi, s->M, norm_sum + 1, s->stream), "scale launch");
+        t0.done();
+    }
+    return QSIM_OK;
+}
+
+int validate_gates(const qsim_state *s, const qsim_gate *gates, size_t n)
+{
+    if (n > 0 && gates == nullptr)
+        return fail(QSIM_EINVAL, "gates is NULL");
+    char why[160];
+    for (size_t k = 0; k < n; ++k)
+        if (!gate_ok(gates[k], s->M, why, sizeof(why)))
+            return fail(QSIM_EINVAL, "gate %zu: %s", k, why);
+    return QSIM_OK;
+}
+
+int ensure_stage(qsim_state *s, size_t bytes)
+{
+    if (s->stage_bytes >= bytes)
+        return QSIM_OK;
+    HIP_TRY(hipStreamSynchronize(s->stream), "stage sync");
+    if (s->d_stage)
+        (void)hipFree(s->d_stage);
+    s->d_stage = nullptr;
+    s->stage_bytes = 0;
+    HIP_TRY(hipMalloc(&s->d_stage, bytes), "stage alloc");
+    s->stage_bytes = bytes;
+    return QSIM_OK;
+}
+
+// Options -> state fields (no device calls).
+int configure(qsim_state *s, int num_qubits, int dtype, const qsim_options &o)
+{
+    if (num_qubits < 1 || num_qubits > QSIM_MAX_QUBITS)
+        return fail(QSIM_EINVAL, "num_qubits %d outside [1, %d]", num_qubits, QSIM_MAX_QUBITS);
+    if (dtype != QSIM_C64 && dtype != QSIM_C128)
+        return fail(QSIM_EINVAL, "dtype %d is neither QSIM_C64 nor QSIM_C128", dtype);
+    if (o.exec_mode != 0 && o.exec_mode != 1)
+        return fail(QSIM_EINVAL, "exec_mode %d", o.exec_mode);
+    if (o.renorm_period < -1)
+        return fail(QSIM_EINVAL, "renorm_period %d", o.renorm_period);
+    const size_t eb = elem_bytes(dtype);
+    const size_t bytes = ((size_t)1 << num_qubits) * eb;
+    if (o.ext_buffer && o.ext_bytes < bytes)
+        return fail(QSIM_EINVAL, "ext_bytes %zu < %zu needed", o.ext_bytes, bytes);
+    if (o.ext_buffer && (reinterpret_cast<uintptr_t>(o.ext_buffer) % 32) != 0)
+        return fail(QSIM_EINVAL, "ext_buffer must be 32-byte aligned");
+    const int dflt_k = dtype == QSIM_C64 ? 13 : 12;
+    const int dflt_g = dtype == QSIM_C64 ? 5 : 4;
+    int k = o.tile_bits > 0 ? o.tile_bits : env_int("QSIM_TILE_BITS", dflt_k);
+    int low = o.low_bits > 0 ? o.low_bits : env_int("QSIM_LOW_BITS", 5);
+    int G = o.group_bits > 0 ? o.group_bits : env_int("QSIM_GROUP_BITS", dflt_g);
+    if (k < 9 || k > kMaxTileBits || low < 1 || low >= k || G < 3 || G > 5 || k - G < 6 ||
+        k - G > 9)
+        return fail(QSIM_EINVAL,
+                    "tile_bits %d / low_bits %d / group bits %d out of range (9 <= tile_bits "
+                    "<= %d, 1 <= low_bits < tile_bits, 6 <= tile_bits - group bits <= 9)",
+                    k, low, G, kMaxTileBits);
+    if (tile_lds_bytes(k, (int)eb) > kMaxLdsBytes)
+        return fail(QSIM_EINVAL, "a %d-qubit tile of this dtype does not fit the 160 KiB LDS", k);
+    s->M = num_qubits;
+    s->dtype = dtype;
+    s->device = o.device;
+    s->exec_mode = o.exec_mode;
+    s->tile_bits = k;
+    s->low_bits = low;
+    s->group_bits = G;
+    s->renorm_period = o.renorm_period == 0 ? (dtype == QSIM_C64 ? 64 : 0)
+                       : (o.renorm_period < 0 ? 0 : o.renorm_period);
+    s->bytes = bytes;
+    return QSIM_OK;
+}
+
+void release(qsim_state *s)
+{
+    if (s == nullptr)
+        return;
+    (void)hipSetDevice(s->device);
+    if (s->stream)
+        (void)hipStreamSynchronize(s->stream);
+    for (PendingTiming &p : s->pending) {
+        (void)hipEventDestroy(p.start);
+        (void)hipEventDestroy(p.stop);
+    }
+    for (hipEvent_t e : s->free_events)
+        (void)hipEventDestroy(e);
+    if (s->own_mem && s->psi)
+        (void)hipFree(s->psi);
+    if (s->d_partial)
+        (void)hipFree(s->d_partial);
+    if (s->d_tile_norm)
+        (void)hipFree(s->d_tile_norm);
+    if (s->d_scalars)
+        (void)hipFree(s->d_scalars);
+    if (s->d_stage)
+        (void)hipFree(s->d_stage);
+    if (s->h_pinned)
+        (void)hipHostFree(s->h_pinned);
+    if (s->own_stream && s->stream)
+        (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+const char *qsim_last_error(void) { return g_err.c_str(); }
+
+int qsim_create(int num_qubits, int dtype, const qsim_options *opt, qsim_state **out)
+{
+    if (out == nullptr)
+        return fail(QSIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    qsim_options o{};
+    if (opt)
+        o = *opt;
+    qsim_state *s = new qsim_state();
+    int rc = configure(s, num_qubits, dtype, o);
+    if (rc != QSIM_OK) {
+        delete s;
+        return rc;
+    }
+    const size_t bytes = s->bytes;
+    const int k = s->tile_bits;
+    int ndev = 0;
+    hipError_t e0 = hipGetDeviceCount(&ndev);
+    if (e0 != hipSuccess) {
+        delete s;
+        return hip_fail(e0, "hipGetDeviceCount");
+    }
+    if (o.device < 0 || o.device >= ndev) {
+        delete s;
+        return fail(QSIM_EINVAL, "device %d outside [0, %d)", o.device, ndev);
+    }
+    hipError_t e = hipSetDevice(o.device);
+    if (e == hipSuccess) {
+        if (o.hip_stream) {
+            s->stream = reinterpret_cast<hipStream_t>(o.hip_stream);
+        } else {
+            e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+            s->own_stream = e == hipSuccess;
+        }
+    }
+    if (e == hipSuccess) {
+        if (o.ext_buffer) {
+            s->psi = o.ext_buffer;
+        } else {
+            e = hipMalloc(&s->psi, bytes);
+            s->own_mem = e == hipSuccess;
+        }
+    }
+    const int kk = std::min(k, num_qubits);
+    const uint64_t tiles = 1ull << (num_qubits - kk);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&s->d_partial, 4 * kReduceBlocks * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&s->d_tile_norm, tiles * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&s->d_scalars, 16 * sizeof(double));
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&s->h_pinned, 16 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = (dtype == QSIM_C64)
+                ? launch_init_basis<float>((cplx<float> *)s->psi, num_qubits, 0, s->stream)
+                : launch_init_basis<double>((cplx<double> *)s->psi, num_qubits, 0, s->stream);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "qsim_create");
+        release(s);
+        return rc;
+    }
+    *out = s;
+    return QSIM_OK;
+}
+
+int qsim_destroy(qsim_state *s)
+{
+    release(s);
+    return QSIM_OK;
+}
+
+int qsim_reset(qsim_state *s, uint64_t basis_index)
+{
+    if (s == nullptr)
+        return fail(QSIM_EINVAL, "state is NULL");
+    if (basis_index >= (1ull << s->M))
+        return fail(QSIM_ERANGE, "basis index %llu >= 2^%d", (unsigned long long)basis_index, s->M);
+    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+    Timed t(s, 2, 0);
+    HIP_TRY(s->dtype == QSIM_C64
+                ? launch_init_basis<float>((cplx<float> *)s->psi, s->M, basis_index, s->stream)
+                : launch_init_basis<double>((cplx<double> *)s->psi, s->M, basis_index, s->stream),
+            "init launch");
+    t.done();
+    s->step = 0;
+    return QSIM_OK;
+}
+
+int qsim_inject_errors(qsim_state *s, const qsim_error_model *em)
+{
+    if (s == nullptr)
+        return fail(QSIM_EINVAL, "state is NULL");
+    if (em == nullptr) {
+        s->armed = false;
+        return QSIM_OK;
+    }
+    if (!(em->sigma >= 0.0) || !std::isfinite(em->sigma))
+        return fail(QSIM_EINVAL, "sigma must be finite and >= 0");
+    if (!(em->p_bitflip >= 0.0 && em->p_bitflip <= 1.0) ||
+        !(em->p_phaseflip >= 0.0 && em->p_phaseflip <= 1.0))
+        return fail(QSIM_EINVAL, "flip probabilities must lie in [0, 1]");
+    s->em = *em;
+    s->armed = true;
+    return QSIM_OK;
+}
+
+int qsim_apply_circuit(qsim_state *s, const qsim_gate *gates, size_t n_gates)
+{
+    if (s == nullptr)
+        return fail(QSIM_EINVAL, "state is NULL");
+    int rc = validate_gates(s, gates, n_gates);
+    if (rc != QSIM_OK)
+        return rc;
+    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+    std::vector<Op> ops;
+    lower_circuit(s, gates, n_gates, ops);
+    rc = s->dtype == QSIM_C64 ? run_ops<float>(s, ops) : run_ops<double>(s, ops);
+    if (rc != QSIM_OK)
+        return rc;
+    s->step += n_gates;
+    s->stats.gates += n_gates;
+    s->stats.flips += ops.size() - n_gates;
+    return QSIM_OK;
+}
+
+int qsim_apply_inverse(qsim_state *s, const qsim_gate *gates, size_t n_gates)
+{
+    if (s == nullptr)
+        return fail(QSIM_EINVAL, "state is NULL");
+    int rc = validate_gates(s, gates, n_gates);
+    if (rc != QSIM_OK)
+        return rc;
+    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+    std::vector<Op> ops;
+    ops.reserve(n_gates);
+    for (size_t k = 0; k < n_gates; ++k) {
+        Op op = lower_gate(gates[n_gates - 1 - k], 0.0, true);
+        op.step = k;
+        op.is_flip = false;
+        op.step_end = true;
+        ops.push_back(op);
+    }
+    const int saved = s->renorm_period;
+    s->renorm_period = 0;
+    rc = s->dtype == QSIM_C64 ? run_ops<float>(s, ops) : run_ops<double>(s, ops);
+    s->renorm_period = saved;
+    return rc;
+}
+
+int qsim_synchronize(qsim_state *s)
+{
+    if (s == nullptr)
+        return fail(QSIM_EINVAL, "state is NULL");
+    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+    HIP_TRY(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    return QSIM_OK;
+}
+
+int qsim_overlap(const qsim_state *a, const qsim_state *b, double out[4])
+{
+    if (a == nullptr || b == nullptr || out == nullptr)
+        return fail(QSIM_EINVAL, "NULL argument");
+    if (a->M != b->M)
+        return fail(QSIM_EINVAL, "register sizes differ (%d vs %d)", a->M, b->M);
+    if (a->device != b->device)
+        return fail(QSIM_EINVAL, "states live on different devices");
+    qsim_state *sa = const_cast<qsim_state *>(a);
+    HIP_TRY(hipSetDevice(a->device), "hipSetDevice");
+    if (a->stream != b->stream) {
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+        HIP_TRY(hipEventRecord(ev, b->stream), "event record");
+        HIP_TRY(hipStreamWaitEvent(a->stream, ev, 0), "stream wait");
+        (void)hipEventDestroy(ev);
+    }
+    Timed t(sa, 2, 0);
+    hipError_t e;
+    if (a->dtype == QSIM_C64 && b->dtype == QSIM_C64)
+        e = launch_overlap<float, float>((const cplx<float> *)a->psi, (const cplx<float> *)b->psi,
+                                         a->M, a->d_partial, a->d_scalars, a->stream);
+    else if (a->dtype == QSIM_C64)
+        e = launch_overlap<float, double>((const cplx<float> *)a->psi,
+                                          (const cplx<double> *)b->psi, a->M, a->d_partial,
+                                          a->d_scalars, a->stream);
+    else if (b->dtype == QSIM_C64)
+        e = launch_overlap<double, float>((const cplx<double> *)a->psi,
+                                          (const cplx<float> *)b->psi, a->M, a->d_partial,
+                                          a->d_scalars, a->stream);
+    else
+        e = launch_overlap<double, double>((const cplx<double> *)a->psi,
+                                           (const cplx<double> *)b->psi, a->M, a->d_partial,
+                                           a->d_scalars, a->stream);
+    HIP_TRY(e, "overlap launch");
+    t.done();
+    HIP_TRY(hipMemcpyAsync(a->h_pinned, a->d_scalars, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                           a->stream), "overlap copy");
+    HIP_TRY(hipStreamSynchronize(a->stream), "overlap sync");
+    if (a->stream != b->stream)
+        HIP_TRY(hipStreamSynchronize(b->stream), "overlap sync");
+    std::memcpy(out, a->h_pinned, 4 * sizeof(double));
+    return QSIM_OK;
+}
+
+int qsim_fidelity(const qsim_state *a, const qsim_state *b, double *out_F)
+{
+    if (out_F == nullptr)
+        return fail(QSIM_EINVAL, "out_F is NULL");
+    double o[4];
+    int rc = qsim_overlap(a, b, o);
+    if (rc != QSIM_OK)
+        return rc;
+    *out_F = (o[0] * o[0] + o[1] * o[1]) / (o[2] * o[3]);
+    return QSIM_OK;
+}
+
+int qsim_norm(const qsim_state *s, double *out)
+{
+    if (s == nullptr || out == nullptr)
+        return fail(QSIM_EINVAL, "NULL argument");
+    qsim_state *m = const_cast<qsim_state *>(s);
+    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+    Timed t(m, 2, 0);
+    HIP_TRY(s->dtype == QSIM_C64
+                ? launch_norm<float>((const cplx<float> *)s->psi, s->M, s->d_partial,
+                                     s->d_scalars, s->stream)
+                : launch_norm<double>((const cplx<double> *)s->psi, s->M, s->d_partial,
+                                      s->d_scalars, s->stream),
+            "norm launch");
+    t.done();
+    HIP_TRY(hipMemcpyAsync(s->h_pinned, s->d_scalars, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                           s->stream), "norm copy");
+    HIP_TRY(hipStreamSynchronize(s->stream), "norm sync");
+    *out = s->h_pinned[2];
+    return QSIM_OK;
+}
+
+int qsim_probs(const qsim_state *s, uint64_t qubit_mask, double *out, size_t out_len)
+{
+    if (s == nullptr || out == nullptr)
+        return fail(QSIM_EINVAL, "NULL argument");
+    const uint64_t full = (1ull << s->M) - 1;
+    if (qubit_mask & ~full)
+        return fail(QSIM_EINVAL, "mask has bits at or above qubit %d", s->M);
+    const int m = __builtin_popcountll(qubit_mask);
+    if (out_len != (1ull << m))
+        return fail(QSIM_EINVAL, "out_len %zu != 2^%d", out_len, m);
+    qsim_state *ms = const_cast<qsim_state *>(s);
+    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+    const size_t out_bytes = out_len * sizeof(double);
+    if (qubit_mask == full) {
+        int rc = ensure_stage(ms, out_bytes);
+        if (rc != QSIM_OK)
+            return rc;
+        Timed t(ms, 2, 0);
+        HIP_TRY(s->dtype == QSIM_C64
+                    ? launch_probs_full<float>((const cplx<float> *)s->psi, s->M,
+                                               (double *)s->d_stage, s->stream)
+                    : launch_probs_full<double>((const cplx<double> *)s->psi, s->M,
+                                                (double *)s->d_stage, s->stream),
+                "probs launch");
+        t.done();
+    } else {
+        const uint64_t plen = probs_marginal_partial_len(s->M, qubit_mask);
+        const size_t out_off = (plen * sizeof(double) + 255) & ~(size_t)255;
+        int rc = ensure_stage(ms, out_off + out_bytes);
+        if (rc != QSIM_OK)
+            return rc;
+        double *partial = (double *)s->d_stage;
+        double *dout = (double *)((char *)s->d_stage + out_off);
+        Timed t(ms, 2, 0);
+        HIP_TRY(s->dtype == QSIM_C64
+                    ? launch_probs_marginal<float>((const cplx<float> *)s->psi, s->M, qubit_mask,
+                                                   partial, plen, dout, s->stream)
+                    : launch_probs_marginal<double>((const cplx<double> *)s->psi, s->M,
+                                                    qubit_mask, partial, plen, dout, s->stream),
+                "marginal launch");
+        t.done();
+        HIP_TRY(hipMemcpyAsync(out, dout, out_bytes, hipMemcpyDeviceToHost, s->stream),
+                "probs copy");
+        HIP_TRY(hipStreamSynchronize(s->stream), "probs sync");
+        return QSIM_OK;
+    }
+    HIP_TRY(hipMemcpyAsync(out, s->d_stage, out_bytes, hipMemcpyDeviceToHost, s->stream),
+            "probs copy");
+    HIP_TRY(hipStreamSynchronize(s->stream), "probs sync");
+    return QSIM_OK;
+}
+
+int qsim_get_amplitudes(const qsim_state *s, uint64_t offset, uint64_t count, double *out)
+{
+    if (s == nullptr || (out == nullptr && count > 0))
+        return fail(QSIM_EINVAL, "NULL argument");
+    const uint64_t n = 1ull << s->M;
+    if (offset > n || count > n - offset)
+        return fail(QSIM_ERANGE, "range [%llu, +%llu) outside 2^%d amplitudes",
+                    (unsigned long long)offset, (unsigned long long)count, s->M);
+    qsim_state *ms = const_cast<qsim_state *>(s);
+    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+    const uint64_t chunk = std::min<uint64_t>(count, 1ull << 22);
+    if (count == 0)
+        return QSIM_OK;
+    int rc = ensure_stage(ms, chunk * 16);
+    if (rc != QSIM_OK)
+        return rc;
+    for (uint64_t done = 0; done < count; done += chunk) {
+        const uint64_t c = std::min(chunk, count - done);
+        HIP_TRY(s->dtype == QSIM_C64
+                    ? launch_to_f64<float>((const cplx<float> *)s->psi + offset + done, c,
+                                           (double *)s->d_stage, s->stream)
+                    : launch_to_f64<double>((const cplx<double> *)s->psi + offset + done, c,
+                                            (double *)s->d_stage, s->stream),
+                "convert launch");
+        HIP_TRY(hipMemcpyAsync(out + 2 * done, s->d_stage, c * 16, hipMemcpyDeviceToHost,
+                               s->stream), "amplitude copy");
+        HIP_TRY(hipStreamSynchronize(s->stream), "amplitude sync");
+    }
+    return QSIM_OK;
+}
+
+int qsim_set_amplitudes(qsim_state *s, uint64_t offset, uint64_t count, const double *in)
+{
+    if (s == nullptr || (in == nullptr && count > 0))
+        return fail(QSIM_EINVAL, "NULL argument");
+    const uint64_t n = 1ull << s->M;
+    if (offset > n || count > n - offset)
+        return fail(QSIM_ERANGE, "range outside the register");
+    for (uint64_t i = 0; i < 2 * count; ++i)
+        if (!std::isfinite(in[i]))
+            return fail(QSIM_EINVAL, "non-finite input at %llu", (unsigned long long)i);
+    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+    if (count == 0)
+        return QSIM_OK;
+    const uint64_t chunk = std::min<uint64_t>(count, 1ull << 22);
+    int rc = ensure_stage(s, chunk * 16);
+    if (rc != QSIM_OK)
+        return rc;
+    for (uint64_t done = 0; done < count; done += chunk) {
+        const uint64_t c = std::min(chunk, count - done);
+        HIP_TRY(hipMemcpyAsync(s->d_stage, in + 2 * done, c * 16, hipMemcpyHostToDevice,
+                               s->stream), "amplitude copy");
+        HIP_TRY(s->dtype == QSIM_C64
+                    ? launch_from_f64<float>((const double *)s->d_stage, c,
+                                             (cplx<float> *)s->psi + offset + done, s->stream)
+                    : launch_from_f64<double>((const double *)s->d_stage, c,
+                                              (cplx<double> *)s->psi + offset + done, s->stream),
+                "convert launch");
+        HIP_TRY(hipStreamSynchronize(s->stream), "amplitude sync");
+    }
+    return QSIM_OK;
+}
+
+int qsim_plan(int num_qubits, int dtype, const qsim_options *opt, const qsim_gate *gates,
+              size_t n_gates, const qsim_error_model *em, uint64_t step0, qsim_pass_info *out,
+              size_t out_cap, size_t *n_passes, size_t *n_ops)
+{
+    qsim_options o{};
+    if (opt)
+        o = *opt;
+    qsim_state st;
+    int rc = configure(&st, num_qubits, dtype, o);
+    if (rc != QSIM_OK)
+        return rc;
+    rc = validate_gates(&st, gates, n_gates);
+    if (rc != QSIM_OK)
+        return rc;
+    if (em) {
+        if (!(em->sigma >= 0.0) || !std::isfinite(em->sigma) || !(em->p_bitflip >= 0.0) ||
+            !(em->p_bitflip <= 1.0) || !(em->p_phaseflip >= 0.0) || !(em->p_phaseflip <= 1.0))
+            return fail(QSIM_EINVAL, "bad error model");
+        st.em = *em;
+        st.armed = true;
+    }
+    st.step = step0;
+    std::vector<Op> ops;
+    lower_circuit(&st, gates, n_gates, ops);
+    std::vector<PassPlan> plan;
+    schedule(&st, ops, plan);
+    if (n_passes)
+        *n_passes = plan.size();
+    if (n_ops)
+        *n_ops = ops.size();
+    for (size_t i = 0; i < plan.size(); ++i) {
+        qsim_pass_info info{};
+        info.fused = plan[i].fused ? 1u : 0u;
+        info.first_op = (uint32_t)plan[i].first;
+        info.n_ops = (uint32_t)plan[i].count;
+        info.norm_after = plan[i].norm_after ? 1u : 0u;
+        if (plan[i].fused) {
+            char why[160];
+            int G = 0;
+            bool ok;
+            if (dtype == QSIM_C64) {
+                TileArgs<float> A;
+                build_tile_args<float>(&st, ops, plan[i], A, G);
+                ok = tile_args_consistent<float>(A, G, ops, plan[i], why, sizeof(why));
+                info.n_groups = A.ngroups;
+                info.tile_mask = A.smask;
+            } else {
+                TileArgs<double> A;
+                build_tile_args<double>(&st, ops, plan[i], A, G);
+                ok = tile_args_consistent<double>(A, G, ops, plan[i], why, sizeof(why));
+                info.n_groups = A.ngroups;
+                info.tile_mask = A.smask;
+            }
+            if (!ok)
+                return fail(QSIM_EDEVICE, "internal: pass %zu inconsistent: %s", i, why);
+        }
+        if (out && i < out_cap)
+            out[i] = info;
+    }
+    return QSIM_OK;
+}
+
+int qsim_info(const qsim_state *s, int *num_qubits, int *dtype, uint64_t *step, void **device_ptr,
+              size_t *bytes)
+{
+    if (s == nullptr)
+        return fail(QSIM_EINVAL, "state is NULL");
+    if (num_qubits) *num_qubits = s->M;
+    if (dtype) *dtype = s->dtype;
+    if (step) *step = s->step;
+    if (device_ptr) *device_ptr = s->psi;
+    if (bytes) *bytes = s->bytes;
+    return QSIM_OK;
+}
+
+int qsim_profile(qsim_state *s, int enable)
+{
+    if (s == nullptr)
+        return fail(QSIM_EINVAL, "state is NULL");
+    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+    int rc = flush_timings(s);
+    if (rc != QSIM_OK)
+        return rc;
+    s->stats = qsim_stats{};
+    s->profiling = enable != 0;
+    return QSIM_OK;
+}
+
+int qsim_get_stats(qsim_state *s, qsim_stats *out)
+{
+    if (s == nullptr || out == nullptr)
+        return fail(QSIM_EINVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+    int rc = flush_timings(s);
+    if (rc != QSIM_OK)
+        return rc;
+    *out = s->stats;
+    return QSIM_OK;
+}
+
+}  // extern "C"

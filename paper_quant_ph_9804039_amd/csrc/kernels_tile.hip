@@ -1,0 +1,392 @@
+// Fused tile pass for gfx950: one HBM read and one HBM write of the state
+// for a whole run of operations.
+//
+// The pair decomposition of Sec. 2.1 means a gate on target t only mixes
+// amplitudes that differ in bit t.  Pick a set S of k qubits; the 2^k
+// amplitudes that share all bits outside S (a "tile") are then closed under
+// every gate whose target lies in S, and under every diagonal gate wherever
+// its target is.  A control outside S is a constant of the tile.  So each
+// workgroup takes one tile, applies the whole run of operations to it, and
+// writes it back once.
+//
+// Inside a pass the operations come in groups whose targets (those that
+// need one) fall on at most G tile bits.  For a group, each of the 2^(k-G)
+// threads holds one "quantum" in registers: the 2^G amplitudes spanned by the
+// group bits, register r holding the amplitude whose group bits spell r.
+// Then every operation of the group is a fixed pattern of register pairs,
+// and the uniform operation stream costs no data movement.  The first
+// group's quanta come straight from HBM and the last group's go straight
+// back; between groups the tile is re-partitioned through LDS.  Threads
+// enumerate the non-group tile bits from the lowest, and the lowest tile bits
+// are the low qubits, so neighbouring lanes touch neighbouring amplitudes.
+#include "launch.h"
+
+namespace qsim {
+namespace {
+
+__device__ __forceinline__ void ld2(const cplx<float> *p, cplx<float> &a, cplx<float> &b)
+{
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    a = {v.x, v.y};
+    b = {v.z, v.w};
+}
+__device__ __forceinline__ void st2(cplx<float> *p, cplx<float> a, cplx<float> b)
+{
+    *reinterpret_cast<float4 *>(p) = make_float4(a.re, a.im, b.re, b.im);
+}
+__device__ __forceinline__ void ld2(const cplx<double> *p, cplx<double> &a, cplx<double> &b)
+{
+    const double2 v0 = reinterpret_cast<const double2 *>(p)[0];
+    const double2 v1 = reinterpret_cast<const double2 *>(p)[1];
+    a = {v0.x, v0.y};
+    b = {v1.x, v1.y};
+}
+__device__ __forceinline__ void st2(cplx<double> *p, cplx<double> a, cplx<double> b)
+{
+    reinterpret_cast<double2 *>(p)[0] = make_double2(a.re, a.im);
+    reinterpret_cast<double2 *>(p)[1] = make_double2(b.re, b.im);
+}
+
+// One operation on the registers of group bit P.  Controls on group bits
+// (mask rc over the register index) select registers with a uniform test per
+// register; the target bit is a compile-time property of r.
+template <typename R, int G, int P>
+__device__ __forceinline__ void apply_at(const TileOp<R> &op, cplx<R> (&x)[1 << G])
+{
+    const uint32_t rc = op.rc;
+    switch (op.kind) {
+    case kTPair: {
+        // out0 = m00 a + m01 b + i w0 a,  out1 = m10 a + m11 b + i w1 b
+        const R m00 = op.c[0], m01 = op.c[1], m10 = op.c[2], m11 = op.c[3];
+        const R w0 = op.c[4], w1 = op.c[5];
+        const bool has_w = op.has_w;
+#pragma unroll
+        for (int r = 0; r < (1 << G); ++r) {
+            if ((r & (1 << P)) || ((uint32_t)r & rc) != rc)
+                continue;
+            const int r1 = r | (1 << P);
+            const cplx<R> a = x[r], b = x[r1];
+            cplx<R> na = {m00 * a.re + m01 * b.re, m00 * a.im + m01 * b.im};
+            cplx<R> nb = {m10 * a.re + m11 * b.re, m10 * a.im + m11 * b.im};
+            if (has_w) {
+                na.re -= w0 * a.im;
+                na.im += w0 * a.re;
+                nb.re -= w1 * b.im;
+                nb.im += w1 * b.re;
+            }
+            x[r] = na;
+            x[r1] = nb;
+        }
+        break;
+    }
+    case kTSwap: {
+#pragma unroll
+        for (int r = 0; r < (1 << G); ++r) {
+            if ((r & (1 << P)) || ((uint32_t)r & rc) != rc)
+                continue;
+            const int r1 = r | (1 << P);
+            const cplx<R> a = x[r];
+            x[r] = x[r1];
+            x[r1] = a;
+        }
+        break;
+    }
+    case kTDiagIn: {
+        const cplx<R> d0 = {op.c[0], op.c[1]}, d1 = {op.c[2], op.c[3]};
+#pragma unroll
+        for (int r = 0; r < (1 << G); ++r) {
+            if (((uint32_t)r & rc) != rc)
+                continue;
+            x[r] = cmul(x[r], ((r >> P) & 1) ? d1 : d0);
+        }
+        break;
+    }
+    default: {  // kTNegIn
+#pragma unroll
+        for (int r = 0; r < (1 << G); ++r) {
+            if (!((r >> P) & 1) || ((uint32_t)r & rc) != rc)
+                continue;
+            x[r] = {-x[r].re, -x[r].im};
+        }
+        break;
+    }
+    }
+}
+
+// Apply the operations [first, first + cnt) of a group to one quantum.
+// Uncontrolled diagonal operations on bits outside the group commute with
+// everything else in the group (those act on group bits only), and their
+// factor is the same for all registers of the quantum: they are multiplied
+// into one factor F, applied once at the end.
+template <typename R, int G>
+__device__ __forceinline__ void apply_group(const TileArgs<R> &A, uint32_t first, uint32_t cnt,
+                                            cplx<R> (&x)[1 << G], uint32_t j0, uint64_t base)
+{
+    static_assert(G >= 3 && G <= 5, "group bits");
+    cplx<R> F = {R(1), R(0)};
+    bool useF = false;
+    for (uint32_t o = first; o < first + cnt; ++o) {
+        const TileOp<R> op = A.ops[o];  // whole descriptor at once: one scalar wait
+        if ((base & op.cm_out) != op.cm_out || (j0 & op.qc) != op.qc)
+            continue;
+        if (op.kind >= kTDiagOut) {
+            const uint32_t bit = op.tpos != kNoPos ? ((j0 >> op.tpos) & 1u)
+                                                  : (uint32_t)((base >> op.tq) & 1u);
+            if (op.kind == kTNegOut) {
+                if (bit) {
+                    F = {-F.re, -F.im};
+                    useF = true;
+                }
+            } else {
+                const cplx<R> d = bit ? cplx<R>{op.c[2], op.c[3]} : cplx<R>{op.c[0], op.c[1]};
+                F = cmul(F, d);
+                useF = true;
+            }
+            continue;
+        }
+        switch (op.gpos) {
+        case 0: apply_at<R, G, 0>(op, x); break;
+        case 1: apply_at<R, G, 1>(op, x); break;
+        case 2: apply_at<R, G, 2>(op, x); break;
+        case 3: if constexpr (G > 3) apply_at<R, G, 3>(op, x); break;
+        default: if constexpr (G > 4) apply_at<R, G, 4>(op, x); break;
+        }
+    }
+    if (useF) {
+#pragma unroll
+        for (int r = 0; r < (1 << G); ++r)
+            x[r] = cmul(x[r], F);
+    }
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t elem_index(uint32_t j0, const uint32_t (&e)[G], int r)
+{
+    uint32_t j = j0;
+#pragma unroll
+    for (int i = 0; i < G; ++i)
+        if (r & (1 << i))
+            j |= e[i];
+    return j;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Global element offset of register r: the sum of the offsets of its set
+// group bits (distinct qubits, so the sums are disjoint ORs).
+template <int G>
+__device__ __forceinline__ uint64_t greg(const uint64_t (&o)[G], int r)
+{
+    uint64_t d = 0;
+#pragma unroll
+    for (int i = 0; i < G; ++i)
+        if (r & (1 << i))
+            d += o[i];
+    return d;
+}
+
+// Spread the bits of v over runs of consecutive qubits (a bit deposit done
+// run by run).  A run word is start | length << 8; the table is copied to
+// scalar registers in one go.
+__device__ __forceinline__ uint64_t spread(uint64_t v, const uint32_t (&runs)[kMaxRuns], uint32_t n)
+{
+    uint64_t g = 0;
+    uint32_t used = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxRuns; ++i) {
+        if ((uint32_t)i < n) {
+            const uint32_t start = runs[i] & 0xFFu, len = runs[i] >> 8;
+            g |= ((v >> used) & ((1ull << len) - 1ull)) << start;
+            used += len;
+        }
+    }
+    return g;
+}
+
+// One fused pass over one tile.  Each of the T threads holds one quantum of
+// 2^G amplitudes in registers (T * 2^G = 2^k).
+template <typename R, int G, int T>
+__global__ void __launch_bounds__(T) k_tile(const TileArgs<R> A)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ double wsum[T / 64];
+    cplx<R> *tile = reinterpret_cast<cplx<R> *>(lds);
+
+    uint32_t srun[kMaxRuns], crun[kMaxRuns];
+#pragma unroll
+    for (int i = 0; i < kMaxRuns; ++i) {
+        srun[i] = A.srun[i];
+        crun[i] = A.crun[i];
+    }
+    const uint32_t nsrun = A.nsrun;
+    // global index of tile element 0: the tile number spread over the qubits
+    // outside the tile, in ascending order
+    const uint64_t tile_id = blockIdx.x;
+    const uint64_t base = spread(tile_id, crun, A.ncrun);
+
+    uint32_t e[G];       // tile-index mask of each group bit
+    uint64_t o[G];       // global offset of each group bit
+    uint32_t j0 = 0;     // tile index of this thread's register 0
+    bool pair0 = false;  // group bit 0 is tile bit 0: registers r, r+1 adjacent
+    cplx<R> x[1 << G];
+
+    for (uint32_t gi = 0; gi < A.ngroups; ++gi) {
+        if (gi > 0) {
+            // registers -> LDS in the old layout
+            if (pair0) {
+#pragma unroll
+                for (int r = 0; r < (1 << G); r += 2)
+                    st2(tile + elem_index<G>(j0, e, r), x[r], x[r + 1]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < (1 << G); ++r)
+                    tile[elem_index<G>(j0, e, r)] = x[r];
+            }
+            __syncthreads();
+        }
+        // this group's layout
+        const uint32_t gw = A.group[gi];
+        j0 = threadIdx.x;
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const uint32_t p = group_bit(gw, i);
+            e[i] = 1u << p;
+            j0 = ((j0 >> p) << (p + 1)) | (j0 & ((1u << p) - 1u));
+        }
+        pair0 = e[0] == 1u;
+        if (gi == 0) {
+            // HBM -> registers
+#pragma unroll
+            for (int i = 0; i < G; ++i)
+                o[i] = spread(e[i], srun, nsrun);
+            const cplx<R> *p = A.psi + (base | spread(j0, srun, nsrun));
+            if (pair0) {
+#pragma unroll
+                for (int r = 0; r < (1 << G); r += 2)
+                    ld2(p + greg<G>(o, r), x[r], x[r + 1]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < (1 << G); ++r)
+                    x[r] = p[greg<G>(o, r)];
+            }
+            if (A.scale_in != nullptr) {
+                const R sc = (R)*A.scale_in;
+#pragma unroll
+                for (int r = 0; r < (1 << G); ++r) {
+                    x[r].re *= sc;
+                    x[r].im *= sc;
+                }
+            }
+        } else {
+            // LDS -> registers in the new layout
+            if (pair0) {
+#pragma unroll
+                for (int r = 0; r < (1 << G); r += 2)
+                    ld2(tile + elem_index<G>(j0, e, r), x[r], x[r + 1]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < (1 << G); ++r)
+                    x[r] = tile[elem_index<G>(j0, e, r)];
+            }
+            __syncthreads();
+        }
+        apply_group<R, G>(A, group_first(gw), group_count(gw), x, j0, base);
+    }
+
+    // registers -> HBM in the last group's layout
+#pragma unroll
+    for (int i = 0; i < G; ++i)
+        o[i] = spread(e[i], srun, nsrun);
+    {
+        cplx<R> *p = A.psi + (base | spread(j0, srun, nsrun));
+        if (pair0) {
+#pragma unroll
+            for (int r = 0; r < (1 << G); r += 2)
+                st2(p + greg<G>(o, r), x[r], x[r + 1]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < (1 << G); ++r)
+                p[greg<G>(o, r)] = x[r];
+        }
+    }
+    if (A.norm_out != nullptr) {
+        double nsum = 0.0;
+#pragma unroll
+        for (int r = 0; r < (1 << G); ++r)
+            nsum += (double)x[r].re * x[r].re + (double)x[r].im * x[r].im;
+        nsum = wave_sum(nsum);
+        if ((threadIdx.x & 63) == 0)
+            wsum[threadIdx.x >> 6] = nsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < T / 64; ++w)
+                t += wsum[w];
+            A.norm_out[tile_id] = t;
+        }
+    }
+}
+
+template <typename R, int G, int T>
+hipError_t launch_gt(const TileArgs<R> &A, hipStream_t st)
+{
+    if (A.k != (uint32_t)G + (uint32_t)__builtin_ctz(T))
+        return hipErrorInvalidValue;
+    const size_t lds = A.ngroups > 1 ? tile_lds_bytes((int)A.k, (int)sizeof(cplx<R>)) : 0;
+    auto fn = k_tile<R, G, T>;
+    // more than 64 KiB of dynamic LDS must be allowed per kernel first
+    static size_t lds_allowed = 65536;  // per instantiation
+    if (lds > lds_allowed) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
+        lds_allowed = lds;
+    }
+    const uint64_t tiles = 1ull << (A.M - A.k);
+    hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(T), lds, st, A);
+    return hipGetLastError();
+}
+
+template <typename R, int G>
+hipError_t launch_g(const TileArgs<R> &A, hipStream_t st)
+{
+    switch ((int)A.k - G) {
+    case 6: return launch_gt<R, G, 64>(A, st);
+    case 7: return launch_gt<R, G, 128>(A, st);
+    case 8: return launch_gt<R, G, 256>(A, st);
+    case 9: return launch_gt<R, G, 512>(A, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+size_t tile_lds_bytes(int k, int elem_bytes)
+{
+    return ((size_t)1 << k) * (size_t)elem_bytes;
+}
+
+template <typename R>
+hipError_t launch_tile(const TileArgs<R> &A, int G, hipStream_t st)
+{
+    switch (G) {
+    case 3: return launch_g<R, 3>(A, st);
+    case 4: return launch_g<R, 4>(A, st);
+    case 5: return launch_g<R, 5>(A, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_tile<float>(const TileArgs<float> &, int, hipStream_t);
+template hipError_t launch_tile<double>(const TileArgs<double> &, int, hipStream_t);
+
+}  // namespace qsim

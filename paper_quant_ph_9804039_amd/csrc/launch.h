@@ -1,0 +1,78 @@
+// Host-side launchers of the qsim kernels (each defined next to its kernels).
+// All take the element type as a template argument: float (complex64 state)
+// or double (complex128 state).  Every launcher enqueues on `st` and returns
+// the hipError_t of the launch.
+#pragma once
+
+#include "common.h"
+
+namespace qsim {
+
+// |k>: zero the vector and set amplitude k to 1 (a fill kernel, not a memset,
+// so it can sit in captured graphs).
+template <typename R>
+hipError_t launch_init_basis(cplx<R> *psi, int M, uint64_t k, hipStream_t st);
+
+// One operation over the whole vector (the per-gate path).
+template <typename R>
+hipError_t launch_plain(const Op &op, cplx<R> *psi, int M, hipStream_t st);
+
+// psi *= *scale (a device scalar).
+template <typename R>
+hipError_t launch_scale(cplx<R> *psi, int M, const double *scale, hipStream_t st);
+
+// One fused tile pass: G group bits per register quantum, 2^(k-G) threads
+// (64..512), so k - G must lie in [6, 9].  LDS (2^k elements) is only used
+// when the pass has more than one group.
+template <typename R>
+hipError_t launch_tile(const TileArgs<R> &args, int G, hipStream_t st);
+size_t tile_lds_bytes(int k, int elem_bytes);
+
+// Deterministic FP64 reductions.  partial must hold 4 * kReduceBlocks
+// doubles; out receives 4 doubles {re<a|b>, im<a|b>, <a|a>, <b|b>}.
+constexpr int kReduceBlocks = 1024;
+template <typename Ra, typename Rb>
+hipError_t launch_overlap(const cplx<Ra> *a, const cplx<Rb> *b, int M, double *partial,
+                          double *out, hipStream_t st);
+// out[0] = <a|a>; partial as above.
+template <typename R>
+hipError_t launch_norm(const cplx<R> *a, int M, double *partial, double *out, hipStream_t st);
+// Sum n per-tile partial norms in order; out[0] = sum, out[1] = 1/sqrt(sum).
+hipError_t launch_finish_norm(const double *tile_norms, uint64_t n, double *out, hipStream_t st);
+
+// Probabilities.  full: out[i] = |a_i|^2.  Marginal: chunk partials, then
+// out[k] summed in chunk order; `partial` holds (2^M / chunk) doubles.
+template <typename R>
+hipError_t launch_probs_full(const cplx<R> *psi, int M, double *out, hipStream_t st);
+template <typename R>
+hipError_t launch_probs_marginal(const cplx<R> *psi, int M, uint64_t mask, double *partial,
+                                 uint64_t partial_len, double *out, hipStream_t st);
+uint64_t probs_marginal_partial_len(int M, uint64_t mask);
+
+// Element conversion between the state and interleaved FP64 staging.
+template <typename R>
+hipError_t launch_to_f64(const cplx<R> *psi, uint64_t count, double *out, hipStream_t st);
+template <typename R>
+hipError_t launch_from_f64(const double *in, uint64_t count, cplx<R> *psi, hipStream_t st);
+
+// Batched Monte Carlo trials (one register per workgroup, persistent grid).
+struct TrialCircuit;  // defined in the trial kernel's source
+struct TrialLaunch {
+    const void *ops;          // device array of lowered circuit operations
+    uint32_t nops;
+    uint32_t M;
+    double sigma, p_bit, p_phase;
+    uint64_t seed, trial0, n_trials;
+    const void *ideal;        // device reference state (same dtype)
+    double *out_F;            // device, n_trials
+    int variant;              // autotuned schedule index
+    int grid;                 // persistent workgroup count
+};
+template <typename R>
+hipError_t launch_trials(const TrialLaunch &L, hipStream_t st);
+template <typename R>
+int trial_variants();
+template <typename R>
+const char *trial_variant_name(int v);
+
+}  // namespace qsim

@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every symbol include/qsim.h declares.
+
+CPU only: no call here touches a GPU.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import circuitgen as cg
+import paper_quant_ph_9804039_amd as q
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qsim.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qsim_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def libpath():
+    if not os.path.exists(q.LIB_PATH):
+        pytest.skip("libqsim.so not built (run __graft_entry__.build())")
+    return q.LIB_PATH
+
+
+def test_header_declares_the_contract():
+    names = _declared()
+    for must in ["qsim_create", "qsim_apply_circuit", "qsim_inject_errors", "qsim_fidelity",
+                 "qsim_probs", "qsim_run_trials", "qsim_destroy", "qsim_last_error"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(libpath):
+    L = ctypes.CDLL(libpath)
+    for name in _declared():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", libpath], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r" T (qsim_\w+)", out))
+    assert set(_declared()) <= exported
+    assert set(q.EXPORTED) == set(_declared())
+
+
+def test_binding_loads_and_reports_no_error(libpath):
+    L = q.lib()
+    assert L.qsim_last_error() == b""
+
+
+def test_struct_layouts():
+    assert cg.GATE_DTYPE.itemsize == 24
+    assert ctypes.sizeof(q.qsim_error_model) == 40
+    assert ctypes.sizeof(q.qsim_stats) == 80
+    text = open(HEADER).read()
+    assert "double theta;" in text and "uint32_t kind;" in text
+
+
+def test_argument_errors_without_gpu(libpath):
+    # rejected before any device call: no GPU needed
+    h = ctypes.c_void_p()
+    L = q.lib()
+    assert L.qsim_create(0, 0, None, ctypes.byref(h)) == q.QSIM_EINVAL
+    assert b"num_qubits" in L.qsim_last_error()
+    assert L.qsim_create(35, 0, None, ctypes.byref(h)) == q.QSIM_EINVAL
+    assert L.qsim_create(4, 7, None, ctypes.byref(h)) == q.QSIM_EINVAL
+    assert L.qsim_create(4, 0, None, None) == q.QSIM_EINVAL
+    g = np.zeros(1, dtype=cg.GATE_DTYPE)
+    out = np.zeros(4)
+    em = q.qsim_error_model(0.1, 0, 0, 1, 0)
+    assert L.qsim_run_trials(g.ctypes.data, 1, 40, 0, ctypes.byref(em), 4,
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == q.QSIM_EINVAL
+    assert L.qsim_destroy(None) == q.QSIM_OK

@@ -1,0 +1,329 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C-ABI.
+
+Bars: permutation gates bit-exact; complex128 within 1e-12 of the oracle
+(fidelity and amplitudes); complex64 within 1e-6 in fidelity and 2e-5 in
+amplitudes (single precision, a few hundred gates).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import circuitgen as cg
+import oracle
+import paper_quant_ph_9804039_amd as q
+
+pytestmark = pytest.mark.gpu
+
+H_EXACT = float.fromhex("0x1.6a09e667f3bcdp-1")
+MODES = [0, 1]  # fused passes, one pass per gate
+
+
+def state(M, dtype=q.QSIM_C128, **kw):
+    return q.State(M, dtype, q.make_options(**kw) if kw else None)
+
+
+def oracle_c(psi):
+    return oracle.as_complex(psi)
+
+
+def set_random(st, M, seed):
+    v = cg.random_state(M, seed)
+    v = v / np.linalg.norm(v)
+    st.set_amplitudes(v)
+    return v
+
+
+# ------------------------------------------------------------------ pins
+
+@pytest.mark.parametrize("dtype", [q.QSIM_C64, q.QSIM_C128])
+def test_fig1_init_and_superposition(dtype):
+    print(f"fig1 dtype={dtype}", flush=True)
+    with state(1, dtype) as s:
+        a = s.amplitudes()
+        assert a[0] == 1.0 and a[1] == 0.0
+        assert np.array_equal(s.probs(), [1.0, 0.0])
+        s.apply(cg.gates_from_list([(cg.H, 0)]))
+        a = s.amplitudes()
+        want = H_EXACT if dtype == q.QSIM_C128 else float(np.float32(H_EXACT))
+        assert a[0] == want and a[1] == want
+        p = s.probs()
+        assert abs(p[0] - 0.5) < (1e-15 if dtype == q.QSIM_C128 else 1e-7)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_fig2_cnot_swaps_a2_a3(mode):
+    with state(2, exec_mode=mode) as s:
+        v = set_random(s, 2, 7)
+        before = s.amplitudes()
+        s.apply(cg.gates_from_list([(cg.CNOT, 0, 1)]))
+        after = s.amplitudes()
+        assert after[0] == before[0] and after[1] == before[1]
+        assert after[2] == before[3] and after[3] == before[2]
+        assert v is not None
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dtype", [q.QSIM_C64, q.QSIM_C128])
+def test_permutation_gates_basis_states_bit_exact(mode, dtype):
+    rng = np.random.default_rng(5)
+    for M in (3, 6, 9):
+        with state(M, dtype, exec_mode=mode) as s:
+            for _ in range(4):
+                t, c0, c1 = (int(x) for x in rng.choice(M, 3, replace=False))
+                for gate, f in [((cg.X, t), lambda k: k ^ (1 << t)),
+                                ((cg.CNOT, t, c0), lambda k: k ^ (((k >> c0) & 1) << t)),
+                                ((cg.TOFFOLI, t, c0, c1),
+                                 lambda k: k ^ ((((k >> c0) & (k >> c1)) & 1) << t))]:
+                    for k in rng.choice(1 << M, min(16, 1 << M), replace=False):
+                        k = int(k)
+                        s.reset(k)
+                        s.apply(cg.gates_from_list([gate]))
+                        a = s.amplitudes()
+                        want = np.zeros(1 << M, complex)
+                        want[f(k)] = 1.0
+                        assert np.array_equal(a, want), (M, gate, k)
+
+
+@pytest.mark.parametrize("mode,group", [(0, 3), (0, 4), (0, 5), (1, 0)])
+def test_permutation_circuit_on_random_state_bit_exact(mode, group):
+    M = 15
+    gates = cg.random_circuit(M, 120, 17, kinds=(cg.X, cg.CNOT, cg.TOFFOLI))
+    for dtype in (q.QSIM_C64, q.QSIM_C128):
+        shape = {"group_bits": group, "tile_bits": group + 8} if group else {}
+        with state(M, dtype, exec_mode=mode, renorm_period=-1, **shape) as s:
+            v = cg.random_state(M, 3)
+            if dtype == q.QSIM_C64:
+                v = v.astype(np.float32).astype(np.float64)
+            s.set_amplitudes(v)
+            s.apply(gates)
+            got = s.amplitudes()
+            ref = oracle.run(v.copy(), M, gates)
+            assert np.array_equal(got, oracle_c(ref))
+
+
+# ---------------------------------------------------------- circuits vs oracle
+
+def _check_vs_oracle(M, gates, dtype, mode, em=None, tol_amp=1e-12, tol_f=1e-12, **kw):
+    ideal_ref = oracle.simulate(M, gates)
+    noisy_ref = oracle.simulate(M, gates, em) if em else ideal_ref
+    with state(M, dtype, exec_mode=mode, **kw) as ideal, state(M, dtype, exec_mode=mode, **kw) as noisy:
+        ideal.apply(gates)
+        if em:
+            noisy.inject_errors(em.sigma, em.p_bitflip, em.p_phaseflip, em.seed, em.trial)
+        noisy.apply(gates)
+        F = ideal.fidelity(noisy)
+        F_ref = oracle.fidelity(ideal_ref, noisy_ref, M)
+        assert abs(F - F_ref) <= tol_f, (F, F_ref)
+        for st, ref in ((ideal, ideal_ref), (noisy, noisy_ref)):
+            a = st.amplitudes()
+            r = oracle_c(ref)
+            a_n = a / np.linalg.norm(a)
+            assert np.max(np.abs(a_n - r)) <= tol_amp
+            cplx = np.vdot(r, a)
+            assert 1.0 - abs(cplx) ** 2 / np.vdot(a, a).real <= max(tol_f, 1e-15)
+    return F, F_ref
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config1_m12_c128_sigma_001(mode):
+    """M=12, complex128, 200 uniform random gates; error-free vs sigma=0.01 trial."""
+    M = 12
+    gates = cg.random_circuit(M, 200, 12)
+    em = oracle.Errors(sigma=0.01, seed=1012, trial=0)
+    F, F_ref = _check_vs_oracle(M, gates, q.QSIM_C128, mode, em)
+    print(f"config1 mode={mode} F={F!r} oracle={F_ref!r} |dF|={abs(F - F_ref):.2e}")
+    assert 0.5 < F < 1.0
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("M", [10, 14, 17])
+def test_c128_with_flips_several_tiles(mode, M):
+    gates = cg.random_circuit(M, 150, 100 + M)
+    em = oracle.Errors(sigma=0.02, p_bitflip=2e-3, p_phaseflip=2e-3, seed=M, trial=3)
+    _check_vs_oracle(M, gates, q.QSIM_C128, mode, em)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("M", [12, 16])
+def test_c64_vs_fp64_oracle(mode, M):
+    gates = cg.random_circuit(M, 200, 200 + M)
+    em = oracle.Errors(sigma=1e-3, p_bitflip=1e-3, p_phaseflip=1e-3, seed=M, trial=1)
+    _check_vs_oracle(M, gates, q.QSIM_C64, mode, em, tol_amp=2e-5, tol_f=1e-6)
+
+
+@pytest.mark.parametrize("tile,low,group", [(9, 1, 3), (10, 3, 4), (11, 5, 5), (12, 6, 3),
+                                            (13, 7, 4), (13, 2, 5), (12, 11, 4)])
+def test_fused_tile_shapes_match_oracle(tile, low, group):
+    M = 15
+    gates = cg.random_circuit(M, 160, 31, kinds=(cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT, cg.TOFFOLI))
+    em = oracle.Errors(sigma=0.05, p_bitflip=2e-3, p_phaseflip=2e-3, seed=5, trial=9)
+    _check_vs_oracle(M, gates, q.QSIM_C128, 0, em, tile_bits=tile, low_bits=low, group_bits=group)
+    _check_vs_oracle(M, gates, q.QSIM_C64, 0, em, tol_amp=2e-5, tol_f=1e-6, tile_bits=tile,
+                     low_bits=low, group_bits=group)
+
+
+def test_c64_largest_tile():
+    M = 16
+    gates = cg.random_circuit(M, 200, 41)
+    em = oracle.Errors(sigma=0.02, p_bitflip=2e-3, p_phaseflip=2e-3, seed=6, trial=2)
+    _check_vs_oracle(M, gates, q.QSIM_C64, 0, em, tol_amp=2e-5, tol_f=1e-6, tile_bits=14,
+                     group_bits=5)
+
+
+@pytest.mark.parametrize("M", [9, 10, 11, 12, 13])
+def test_small_registers_fused_shapes(M):
+    gates = cg.random_circuit(M, 120, 50 + M)
+    em = oracle.Errors(sigma=0.03, p_bitflip=3e-3, p_phaseflip=3e-3, seed=M, trial=5)
+    _check_vs_oracle(M, gates, q.QSIM_C128, 0, em)
+
+
+def test_bad_tile_options_rejected():
+    for kw in ({"tile_bits": 8}, {"tile_bits": 15}, {"tile_bits": 13, "group_bits": 2},
+               {"tile_bits": 13, "low_bits": 13}, {"tile_bits": 10, "group_bits": 5}):
+        with pytest.raises(q.QsimError) as e:
+            state(12, **kw)
+        assert e.value.code == q.QSIM_EINVAL
+    with pytest.raises(q.QsimError):
+        state(12, q.QSIM_C128, tile_bits=14, group_bits=5)
+
+
+def test_dense_brute_force_small_registers():
+    from oracle import dense
+    for M in (1, 2, 3, 6, 9):
+        kinds = (cg.H, cg.RZ, cg.X, cg.Z) if M < 3 else (cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT, cg.TOFFOLI)
+        if M == 2:
+            kinds = kinds + (cg.CNOT,)
+        gates = cg.random_circuit(M, 40, M, kinds=kinds)
+        em = oracle.Errors(sigma=0.2, p_bitflip=0.03, p_phaseflip=0.03, seed=M, trial=2)
+        want = dense.simulate(M, gates, em)
+        for mode in MODES:
+            with state(M, exec_mode=mode) as s:
+                s.inject_errors(em.sigma, em.p_bitflip, em.p_phaseflip, em.seed, em.trial)
+                s.apply(gates)
+                assert np.max(np.abs(s.amplitudes() - want)) < 1e-12, (M, mode)
+
+
+# --------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("mode", MODES)
+def test_norm_inverse_and_determinism(mode):
+    M = 16
+    gates = cg.random_circuit(M, 300, 77)
+    with state(M, exec_mode=mode) as s:
+        s.apply(gates)
+        assert abs(s.norm() - 1.0) < 1e-12
+        s.apply_inverse(gates)
+        a = s.amplitudes()
+        e0 = np.zeros(1 << M, complex)
+        e0[0] = 1
+        assert np.max(np.abs(a - e0)) < 1e-12
+    with state(M, exec_mode=mode) as a, state(M, exec_mode=mode) as b:
+        a.apply(gates[:150])
+        b.apply(gates[:149])
+        f1, f2 = a.fidelity(b), a.fidelity(b)
+        assert f1 == f2 and f1 < 1
+
+
+def test_error_free_model_bit_identical_and_split_calls():
+    """sigma = p = 0 armed equals disarmed bit for bit; a circuit split over two
+    calls draws the same errors as the whole circuit (bit-identical per gate
+    pass; fused passes may group the operations differently, so there the
+    results agree to rounding)."""
+    M = 13
+    gates = cg.random_circuit(M, 200, 3)
+    for dtype, tol in ((q.QSIM_C64, 2e-6), (q.QSIM_C128, 1e-14)):
+        for mode in MODES:
+            with state(M, dtype, exec_mode=mode) as a, state(M, dtype, exec_mode=mode) as b:
+                a.apply(gates)
+                b.inject_errors(0.0, 0.0, 0.0, seed=9, trial=4)
+                b.apply(gates)
+                assert np.array_equal(a.amplitudes(), b.amplitudes())
+            with state(M, dtype, exec_mode=mode) as c, state(M, dtype, exec_mode=mode) as d:
+                c.inject_errors(0.01, 1e-3, 1e-3, seed=9, trial=4)
+                c.apply(gates[:77])
+                c.apply(gates[77:])
+                d.inject_errors(0.01, 1e-3, 1e-3, seed=9, trial=4)
+                d.apply(gates)
+                ac, ad = c.amplitudes(), d.amplitudes()
+                if mode == 1:
+                    assert np.array_equal(ac, ad)
+                assert np.max(np.abs(ac - ad)) < tol
+                assert 1.0 - c.fidelity(d) < tol
+                assert c.info()["step"] == 200
+
+
+@pytest.mark.parametrize("dtype", [q.QSIM_C64, q.QSIM_C128])
+def test_ghz_exact_m24(dtype):
+    M = 24
+    with state(M, dtype) as s:
+        s.apply(cg.ghz_circuit(M))
+        a = s.amplitudes()
+        h = H_EXACT if dtype == q.QSIM_C128 else float(np.float32(H_EXACT))
+        assert a[0] == h and a[-1] == h
+        assert np.count_nonzero(a) == 2
+
+
+def test_fidelity_mixed_dtypes_and_closed_forms():
+    M = 1
+    with state(M, q.QSIM_C64) as a, state(M, q.QSIM_C128) as b:
+        a.apply(cg.gates_from_list([(cg.H, 0)]))
+        b.apply(cg.gates_from_list([(cg.H, 0)]))
+        assert abs(a.fidelity(b) - 1.0) < 1e-7
+    for trial in range(5):
+        em = oracle.Errors(sigma=0.2, seed=3, trial=trial)
+        eps = oracle.angle_error(em, 0)
+        with state(1) as ideal, state(1) as noisy:
+            g = cg.gates_from_list([(cg.X, 0)])
+            ideal.apply(g)
+            noisy.inject_errors(0.2, seed=3, trial=trial)
+            noisy.apply(g)
+            assert abs(ideal.fidelity(noisy) - math.cos(eps / 2) ** 2) < 1e-15
+
+
+@pytest.mark.parametrize("dtype", [q.QSIM_C64, q.QSIM_C128])
+def test_probs_full_and_marginal(dtype):
+    M = 14
+    gates = cg.random_circuit(M, 120, 4)
+    ref = oracle.simulate(M, gates)
+    tol = 1e-15 if dtype == q.QSIM_C128 else 1e-6
+    with state(M, dtype) as s:
+        s.apply(gates)
+        assert np.max(np.abs(s.probs() - oracle.probs(ref, M))) < tol
+        for mask in (0, 1, 0b1010, (1 << 10) - 1, 1 << 13, 0b10110000001011):
+            got = s.probs(mask)
+            want = oracle.probs(ref, M, mask)
+            assert got.shape == want.shape
+            assert np.max(np.abs(got - want)) < 50 * tol, mask
+
+
+def test_renormalisation_keeps_c64_norm():
+    M = 16
+    gates = cg.random_circuit(M, 400, 8)
+    ref = oracle_c(oracle.simulate(M, gates))
+    for mode in MODES:
+        with state(M, q.QSIM_C64, exec_mode=mode, renorm_period=16) as s:
+            s.apply(gates)
+            assert abs(s.norm() - 1.0) < 1e-6
+            a = s.amplitudes()
+            assert np.max(np.abs(a - ref)) < 5e-5
+            st = s.stats()
+            assert st["renorms"] == 400 // 16
+
+
+def test_invalid_gates_rejected_and_state_untouched():
+    with state(4) as s:
+        s.apply(cg.gates_from_list([(cg.H, 0)]))
+        before = s.amplitudes()
+        for bad in ([(cg.CNOT, 1, 1)], [(cg.H, 4)], [(cg.TOFFOLI, 0, 2, 2)], [(9, 0)]):
+            with pytest.raises(q.QsimError) as e:
+                s.apply(cg.gates_from_list([(cg.X, 1)] + bad))
+            assert e.value.code == q.QSIM_EINVAL
+        assert np.array_equal(s.amplitudes(), before)
+        with pytest.raises(q.QsimError):
+            s.reset(16)
+        with pytest.raises(q.QsimError):
+            s.inject_errors(0.1, p_bitflip=2.0)
+        with pytest.raises(q.QsimError):
+            s.probs(1 << 4)
+        assert s.info()["step"] == 1

@@ -1,0 +1,89 @@
+"""Host logic of the library on the CPU: the pass schedule (qsim_plan runs
+the lowering, the error draws, the scheduler and the kernel-argument builder
+without a device, and checks each pass's arguments itself)."""
+import numpy as np
+import pytest
+
+import circuitgen as cg
+import oracle
+import paper_quant_ph_9804039_amd as q
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    try:
+        q.lib()
+    except ImportError as e:
+        pytest.skip(str(e))
+
+
+SHAPES = [(13, 5, 5), (13, 5, 4), (12, 5, 4), (14, 5, 5), (9, 1, 3), (10, 3, 4), (11, 5, 5),
+          (12, 11, 4), (13, 2, 5), (12, 6, 3)]
+
+
+@pytest.mark.parametrize("tile,low,group", SHAPES)
+@pytest.mark.parametrize("M", [9, 12, 16, 30])
+def test_plan_covers_every_op_in_order(M, tile, low, group):
+    gates = cg.random_circuit(M, 300, M * 7 + tile, kinds=(cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT,
+                                                             cg.TOFFOLI))
+    opt = q.make_options(tile_bits=tile, low_bits=low, group_bits=group)
+    passes, nops = q.qsim_plan(M, q.QSIM_C64, gates, opt, sigma=0.01, p_bitflip=0.01,
+                               p_phaseflip=0.01, seed=3, trial=1)
+    nxt = 0
+    for p in passes:
+        assert p["first_op"] == nxt and p["n_ops"] >= 1
+        nxt += p["n_ops"]
+        if p["fused"]:
+            assert bin(p["tile_mask"]).count("1") == min(tile, M)
+            assert p["n_ops"] <= 32 and 1 <= p["n_groups"] <= p["n_ops"]
+    assert nxt == nops
+
+
+def test_flip_count_matches_oracle_draws():
+    M, G = 12, 200
+    gates = cg.random_circuit(M, G, 4)
+    em = oracle.Errors(sigma=0.0, p_bitflip=0.01, p_phaseflip=0.02, seed=77, trial=5)
+    want = sum(bin(oracle.flip_events(em, s, qb)).count("1") for s in range(G) for qb in range(M))
+    _, nops = q.qsim_plan(M, q.QSIM_C128, gates, None, sigma=0.0, p_bitflip=0.01,
+                          p_phaseflip=0.02, seed=77, trial=5)
+    assert nops == G + want
+    _, nops2 = q.qsim_plan(M, q.QSIM_C128, gates[100:], None, sigma=0.0, p_bitflip=0.01,
+                           p_phaseflip=0.02, seed=77, trial=5, step0=100)
+    want2 = sum(bin(oracle.flip_events(em, s, qb)).count("1") for s in range(100, G) for qb in range(M))
+    assert nops2 == G - 100 + want2
+
+
+def test_fusion_factor_of_uniform_random_circuit():
+    # targets uniform over 30 qubits: a 13-qubit tile with 5 low qubits holds
+    # runs of about a dozen gates
+    gates = cg.random_circuit(30, 1000, 30)
+    passes, _ = q.qsim_plan(30, q.QSIM_C64, gates)
+    assert all(p["fused"] for p in passes)
+    assert 1000 / len(passes) > 8
+
+
+def test_renorm_boundaries_end_passes():
+    gates = cg.random_circuit(16, 256, 1)
+    passes, _ = q.qsim_plan(16, q.QSIM_C64, gates, q.make_options(renorm_period=32))
+    assert sum(p["norm_after"] for p in passes) == 256 // 32
+    plain, _ = q.qsim_plan(16, q.QSIM_C64, gates, q.make_options(exec_mode=1))
+    assert len(plain) == 256 and not any(p["fused"] for p in plain)
+
+
+def test_small_registers_use_per_gate_passes():
+    for M in range(1, 9):
+        gates = cg.random_circuit(M, 20, M, kinds=(cg.H, cg.RZ, cg.X))
+        passes, _ = q.qsim_plan(M, q.QSIM_C128, gates)
+        assert not any(p["fused"] for p in passes)
+    passes, _ = q.qsim_plan(9, q.QSIM_C128, cg.random_circuit(9, 20, 9))
+    assert all(p["fused"] for p in passes)
+
+
+def test_plan_rejects_bad_input():
+    with pytest.raises(q.QsimError):
+        q.qsim_plan(5, q.QSIM_C64, cg.gates_from_list([(cg.CNOT, 1, 1)]))
+    with pytest.raises(q.QsimError):
+        q.qsim_plan(5, q.QSIM_C64, cg.gates_from_list([(cg.H, 1)]), sigma=-1.0)
+    with pytest.raises(q.QsimError):
+        q.qsim_plan(20, q.QSIM_C128, cg.gates_from_list([(cg.H, 1)]),
+                    q.make_options(tile_bits=14, group_bits=5))
