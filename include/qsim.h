@@ -104,10 +104,9 @@ typedef struct {
     int tile_bits;       /* qubits per fused tile, 9..14; 0: default (13 for
                             QSIM_C64, 12 for QSIM_C128) */
     int low_bits;        /* low qubits always in a fused tile, 1..tile_bits-1;
-                            0: default (5) */
+                            0: default (4) */
     int group_bits;      /* qubits per register quantum, 3..5, with
-                            6 <= tile_bits - group_bits <= 9; 0: default (5 for
-                            QSIM_C64, 4 for QSIM_C128) */
+                            6 <= tile_bits - group_bits <= 9; 0: default (4) */
 } qsim_options;
 
 /* Per-state counters of the work launched since the last reset of the

@@ -747,9 +747,9 @@ int configure(qsim_state *s, int num_qubits, int dtype, const qsim_options &o)
     if (o.ext_buffer && (reinterpret_cast<uintptr_t>(o.ext_buffer) % 32) != 0)
         return fail(QSIM_EINVAL, "ext_buffer must be 32-byte aligned");
     const int dflt_k = dtype == QSIM_C64 ? 13 : 12;
-    const int dflt_g = dtype == QSIM_C64 ? 5 : 4;
+    const int dflt_g = 4;
     int k = o.tile_bits > 0 ? o.tile_bits : env_int("QSIM_TILE_BITS", dflt_k);
-    int low = o.low_bits > 0 ? o.low_bits : env_int("QSIM_LOW_BITS", 5);
+    int low = o.low_bits > 0 ? o.low_bits : env_int("QSIM_LOW_BITS", 4);
     int G = o.group_bits > 0 ? o.group_bits : env_int("QSIM_GROUP_BITS", dflt_g);
     if (k < 9 || k > kMaxTileBits || low < 1 || low >= k || G < 3 || G > 5 || k - G < 6 ||
         k - G > 9)

@@ -209,8 +209,60 @@ __device__ __forceinline__ uint64_t spread(uint64_t v, const uint32_t (&runs)[kM
     return g;
 }
 
-// One fused pass over one tile.  Each of the T threads holds one quantum of
-// 2^G amplitudes in registers (T * 2^G = 2^k).
+// Register quantum <-> memory in a given layout (two adjacent registers per
+// access when group bit 0 is tile bit 0).
+template <typename R, int G>
+__device__ __forceinline__ void load_quantum(const cplx<R> *p, const uint64_t (&o)[G], bool pair0,
+                                             cplx<R> (&x)[1 << G])
+{
+    if (pair0) {
+#pragma unroll
+        for (int r = 0; r < (1 << G); r += 2)
+            ld2(p + greg<G>(o, r), x[r], x[r + 1]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < (1 << G); ++r)
+            x[r] = p[greg<G>(o, r)];
+    }
+}
+
+template <typename R, int G>
+__device__ __forceinline__ void store_quantum(cplx<R> *p, const uint64_t (&o)[G], bool pair0,
+                                              const cplx<R> (&x)[1 << G])
+{
+    if (pair0) {
+#pragma unroll
+        for (int r = 0; r < (1 << G); r += 2)
+            st2(p + greg<G>(o, r), x[r], x[r + 1]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < (1 << G); ++r)
+            p[greg<G>(o, r)] = x[r];
+    }
+}
+
+// Layout of group gi for this thread: tile-index masks of the group bits,
+// tile index of register 0, and whether registers r, r+1 are adjacent.
+template <typename R, int G>
+__device__ __forceinline__ void group_layout(const TileArgs<R> &A, uint32_t gi, uint32_t (&e)[G],
+                                             uint32_t &j0, bool &pair0)
+{
+    const uint32_t gw = A.group[gi];
+    j0 = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        const uint32_t p = group_bit(gw, i);
+        e[i] = 1u << p;
+        j0 = ((j0 >> p) << (p + 1)) | (j0 & ((1u << p) - 1u));
+    }
+    pair0 = e[0] == 1u;
+}
+
+// Fused pass, persistent: each workgroup walks tiles blockIdx.x, +gridDim.x,
+// ...  Each of the T threads holds one quantum of 2^G amplitudes in
+// registers (T * 2^G = 2^k).  While a tile is being worked on, the first
+// group's quanta of the workgroup's next tile are already being loaded, so
+// HBM traffic overlaps the register and LDS work.
 template <typename R, int G, int T>
 __global__ void __launch_bounds__(T) k_tile(const TileArgs<R> A)
 {
@@ -224,21 +276,47 @@ __global__ void __launch_bounds__(T) k_tile(const TileArgs<R> A)
         srun[i] = A.srun[i];
         crun[i] = A.crun[i];
     }
-    const uint32_t nsrun = A.nsrun;
-    // global index of tile element 0: the tile number spread over the qubits
-    // outside the tile, in ascending order
-    const uint64_t tile_id = blockIdx.x;
-    const uint64_t base = spread(tile_id, crun, A.ncrun);
+    const uint32_t nsrun = A.nsrun, ncrun = A.ncrun;
+    const uint64_t ntiles = 1ull << (A.M - A.k);
 
-    uint32_t e[G];       // tile-index mask of each group bit
-    uint64_t o[G];       // global offset of each group bit
-    uint32_t j0 = 0;     // tile index of this thread's register 0
-    bool pair0 = false;  // group bit 0 is tile bit 0: registers r, r+1 adjacent
-    cplx<R> x[1 << G];
+    // the first group's layout is the same for every tile
+    uint32_t e0[G], j00;
+    bool pair00;
+    group_layout<R, G>(A, 0, e0, j00, pair00);
+    uint64_t o0[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i)
+        o0[i] = spread(e0[i], srun, nsrun);
+    const uint64_t rel0 = spread(j00, srun, nsrun);
 
-    for (uint32_t gi = 0; gi < A.ngroups; ++gi) {
-        if (gi > 0) {
-            // registers -> LDS in the old layout
+    cplx<R> x[1 << G], xn[1 << G];
+    uint64_t tile_id = blockIdx.x;
+    if (tile_id < ntiles)
+        load_quantum<R, G>(A.psi + (spread(tile_id, crun, ncrun) | rel0), o0, pair00, x);
+
+    for (; tile_id < ntiles; tile_id += gridDim.x) {
+        // global index of tile element 0: the tile number spread over the
+        // qubits outside the tile, in ascending order
+        const uint64_t base = spread(tile_id, crun, ncrun);
+        const uint64_t next = tile_id + gridDim.x;
+        if (next < ntiles)
+            load_quantum<R, G>(A.psi + (spread(next, crun, ncrun) | rel0), o0, pair00, xn);
+        if (A.scale_in != nullptr) {
+            const R sc = (R)*A.scale_in;
+#pragma unroll
+            for (int r = 0; r < (1 << G); ++r) {
+                x[r].re *= sc;
+                x[r].im *= sc;
+            }
+        }
+        uint32_t e[G], j0 = j00;
+        bool pair0 = pair00;
+#pragma unroll
+        for (int i = 0; i < G; ++i)
+            e[i] = e0[i];
+        apply_group<R, G>(A, group_first(A.group[0]), group_count(A.group[0]), x, j0, base);
+        for (uint32_t gi = 1; gi < A.ngroups; ++gi) {
+            // registers -> LDS in the old layout, LDS -> registers in the new one
             if (pair0) {
 #pragma unroll
                 for (int r = 0; r < (1 << G); r += 2)
@@ -249,42 +327,7 @@ __global__ void __launch_bounds__(T) k_tile(const TileArgs<R> A)
                     tile[elem_index<G>(j0, e, r)] = x[r];
             }
             __syncthreads();
-        }
-        // this group's layout
-        const uint32_t gw = A.group[gi];
-        j0 = threadIdx.x;
-#pragma unroll
-        for (int i = 0; i < G; ++i) {
-            const uint32_t p = group_bit(gw, i);
-            e[i] = 1u << p;
-            j0 = ((j0 >> p) << (p + 1)) | (j0 & ((1u << p) - 1u));
-        }
-        pair0 = e[0] == 1u;
-        if (gi == 0) {
-            // HBM -> registers
-#pragma unroll
-            for (int i = 0; i < G; ++i)
-                o[i] = spread(e[i], srun, nsrun);
-            const cplx<R> *p = A.psi + (base | spread(j0, srun, nsrun));
-            if (pair0) {
-#pragma unroll
-                for (int r = 0; r < (1 << G); r += 2)
-                    ld2(p + greg<G>(o, r), x[r], x[r + 1]);
-            } else {
-#pragma unroll
-                for (int r = 0; r < (1 << G); ++r)
-                    x[r] = p[greg<G>(o, r)];
-            }
-            if (A.scale_in != nullptr) {
-                const R sc = (R)*A.scale_in;
-#pragma unroll
-                for (int r = 0; r < (1 << G); ++r) {
-                    x[r].re *= sc;
-                    x[r].im *= sc;
-                }
-            }
-        } else {
-            // LDS -> registers in the new layout
+            group_layout<R, G>(A, gi, e, j0, pair0);
             if (pair0) {
 #pragma unroll
                 for (int r = 0; r < (1 << G); r += 2)
@@ -295,41 +338,34 @@ __global__ void __launch_bounds__(T) k_tile(const TileArgs<R> A)
                     x[r] = tile[elem_index<G>(j0, e, r)];
             }
             __syncthreads();
+            apply_group<R, G>(A, group_first(A.group[gi]), group_count(A.group[gi]), x, j0, base);
         }
-        apply_group<R, G>(A, group_first(gw), group_count(gw), x, j0, base);
-    }
-
-    // registers -> HBM in the last group's layout
+        // registers -> HBM in the last group's layout
+        uint64_t o[G];
 #pragma unroll
-    for (int i = 0; i < G; ++i)
-        o[i] = spread(e[i], srun, nsrun);
-    {
-        cplx<R> *p = A.psi + (base | spread(j0, srun, nsrun));
-        if (pair0) {
-#pragma unroll
-            for (int r = 0; r < (1 << G); r += 2)
-                st2(p + greg<G>(o, r), x[r], x[r + 1]);
-        } else {
+        for (int i = 0; i < G; ++i)
+            o[i] = spread(e[i], srun, nsrun);
+        store_quantum<R, G>(A.psi + (base | spread(j0, srun, nsrun)), o, pair0, x);
+        if (A.norm_out != nullptr) {
+            double nsum = 0.0;
 #pragma unroll
             for (int r = 0; r < (1 << G); ++r)
-                p[greg<G>(o, r)] = x[r];
+                nsum += (double)x[r].re * x[r].re + (double)x[r].im * x[r].im;
+            nsum = wave_sum(nsum);
+            if ((threadIdx.x & 63) == 0)
+                wsum[threadIdx.x >> 6] = nsum;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double t = 0.0;
+                for (int w = 0; w < T / 64; ++w)
+                    t += wsum[w];
+                A.norm_out[tile_id] = t;
+            }
+            __syncthreads();
         }
-    }
-    if (A.norm_out != nullptr) {
-        double nsum = 0.0;
 #pragma unroll
         for (int r = 0; r < (1 << G); ++r)
-            nsum += (double)x[r].re * x[r].re + (double)x[r].im * x[r].im;
-        nsum = wave_sum(nsum);
-        if ((threadIdx.x & 63) == 0)
-            wsum[threadIdx.x >> 6] = nsum;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int w = 0; w < T / 64; ++w)
-                t += wsum[w];
-            A.norm_out[tile_id] = t;
-        }
+            x[r] = xn[r];
     }
 }
 
@@ -351,8 +387,28 @@ hipError_t launch_gt(const TileArgs<R> &A, hipStream_t st)
         }
         lds_allowed = lds;
     }
+    // persistent grid: as many workgroups as fit on the chip at once
+    static int occ_cache[2] = {0, 0};  // [uses LDS], per instantiation
+    int &occ = occ_cache[lds > 0 ? 1 : 0];
+    if (occ == 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, T, lds) != hipSuccess ||
+            per_cu < 1) {
+            (void)hipGetLastError();
+            per_cu = 1;
+        }
+        int dev = 0, cus = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus < 1) {
+            (void)hipGetLastError();
+            cus = 256;
+        }
+        occ = per_cu * cus;
+    }
     const uint64_t tiles = 1ull << (A.M - A.k);
-    hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(T), lds, st, A);
+    const uint64_t grid = tiles < (uint64_t)occ ? tiles : (uint64_t)occ;
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(T), lds, st, A);
     return hipGetLastError();
 }
 
