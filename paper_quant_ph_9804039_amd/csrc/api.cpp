@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "common.h"
+#include "internal.h"
 #include "launch.h"
 #include "qsim.h"
 
@@ -56,6 +57,21 @@ struct PendingTiming {
 };
 
 }  // namespace
+
+namespace qsim {
+
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+}  // namespace qsim
 
 // ------------------------------------------------------------------- state
 
@@ -176,7 +192,9 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;  // gfx950 LDS per workgroup
 
 constexpr double kSqrtHalf = 0.70710678118654752440084436210485;
 
-bool gate_ok(const qsim_gate &g, int M, char *why, size_t n)
+}  // namespace
+
+bool qsim::gate_valid(const qsim_gate &g, int M, char *why, size_t n)
 {
     int need;
     switch (g.kind) {
@@ -215,6 +233,14 @@ bool gate_ok(const qsim_gate &g, int M, char *why, size_t n)
     }
     return true;
 }
+
+bool qsim::error_model_valid(const qsim_error_model &em)
+{
+    return em.sigma >= 0.0 && std::isfinite(em.sigma) && em.p_bitflip >= 0.0 &&
+           em.p_bitflip <= 1.0 && em.p_phaseflip >= 0.0 && em.p_phaseflip <= 1.0;
+}
+
+namespace {
 
 // The 2x2 of a gate with angle error eps (FP64).  eps == 0 gives the textbook
 // gate; otherwise the gate is i R_n(pi + eps) about its own axis n, and Rz(t)
@@ -710,7 +736,7 @@ int validate_gates(const qsim_state *s, const qsim_gate *gates, size_t n)
         return fail(QSIM_EINVAL, "gates is NULL");
     char why[160];
     for (size_t k = 0; k < n; ++k)
-        if (!gate_ok(gates[k], s->M, why, sizeof(why)))
+        if (!gate_valid(gates[k], s->M, why, sizeof(why)))
             return fail(QSIM_EINVAL, "gate %zu: %s", k, why);
     return QSIM_OK;
 }
@@ -907,11 +933,8 @@ int qsim_inject_errors(qsim_state *s, const qsim_error_model *em)
         s->armed = false;
         return QSIM_OK;
     }
-    if (!(em->sigma >= 0.0) || !std::isfinite(em->sigma))
-        return fail(QSIM_EINVAL, "sigma must be finite and >= 0");
-    if (!(em->p_bitflip >= 0.0 && em->p_bitflip <= 1.0) ||
-        !(em->p_phaseflip >= 0.0 && em->p_phaseflip <= 1.0))
-        return fail(QSIM_EINVAL, "flip probabilities must lie in [0, 1]");
+    if (!error_model_valid(*em))
+        return fail(QSIM_EINVAL, "sigma must be finite and >= 0, flip probabilities in [0, 1]");
     s->em = *em;
     s->armed = true;
     return QSIM_OK;
@@ -1177,8 +1200,7 @@ int qsim_plan(int num_qubits, int dtype, const qsim_options *opt, const qsim_gat
     if (rc != QSIM_OK)
         return rc;
     if (em) {
-        if (!(em->sigma >= 0.0) || !std::isfinite(em->sigma) || !(em->p_bitflip >= 0.0) ||
-            !(em->p_bitflip <= 1.0) || !(em->p_phaseflip >= 0.0) || !(em->p_phaseflip <= 1.0))
+        if (!error_model_valid(*em))
             return fail(QSIM_EINVAL, "bad error model");
         st.em = *em;
         st.armed = true;

@@ -56,23 +56,32 @@ template <typename R>
 hipError_t launch_from_f64(const double *in, uint64_t count, cplx<R> *psi, hipStream_t st);
 
 // Batched Monte Carlo trials (one register per workgroup, persistent grid).
-struct TrialCircuit;  // defined in the trial kernel's source
+struct TrialGate {
+    uint32_t kind;     // qsim_kind
+    uint32_t target;
+    uint32_t cmask;    // control qubits
+    uint32_t pad;
+    double theta;
+    double pad2;
+};
 struct TrialLaunch {
-    const void *ops;          // device array of lowered circuit operations
-    uint32_t nops;
+    const TrialGate *gates;   // device array of the circuit's gates
+    uint32_t ngates;
     uint32_t M;
     double sigma, p_bit, p_phase;
     uint64_t seed, trial0, n_trials;
-    const void *ideal;        // device reference state (same dtype)
+    const void *ideal;        // device error-free register (same dtype)
     double *out_F;            // device, n_trials
-    int variant;              // autotuned schedule index
+    int variant;              // schedule chosen by the autotuner
     int grid;                 // persistent workgroup count
 };
+size_t trial_lds_bytes(int M, int elem_bytes);
 template <typename R>
 hipError_t launch_trials(const TrialLaunch &L, hipStream_t st);
-template <typename R>
 int trial_variants();
-template <typename R>
 const char *trial_variant_name(int v);
+// Persistent workgroups that fit the chip at once (0 if the variant cannot
+// run at this size).
+int trial_grid(int variant, int M, int elem_bytes);
 
 }  // namespace qsim

@@ -1,8 +1,275 @@
-// Batched Monte Carlo trials entry point.
+// qsim_run_trials: batched Monte Carlo error trials in one persistent launch,
+// with a small autotuner that picks the kernel variant per problem shape.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "common.h"
+#include "internal.h"
+#include "launch.h"
 #include "qsim.h"
 
-extern "C" int qsim_run_trials(const qsim_gate *, size_t, int, int, const qsim_error_model *,
-                               uint64_t, double *)
+using namespace qsim;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf()
+    {
+        if (p)
+            (void)hipFree(p);
+    }
+};
+
+struct StateGuard {
+    qsim_state *s = nullptr;
+    ~StateGuard() { qsim_destroy(s); }
+};
+
+int hip_err(hipError_t e, const char *what)
 {
-    return QSIM_EINVAL;
+    (void)hipGetLastError();
+    return set_error(e == hipErrorOutOfMemory ? QSIM_ENOMEM : QSIM_EDEVICE, "%s: %s", what,
+                     hipGetErrorString(e));
 }
+
+// ------------------------------------------------------------------ autotuner
+//
+// Key: register size, dtype, gate count and whether angle errors and flips
+// are drawn.  The choice is kept for the process, and in the file named by
+// QSIM_TUNE_CACHE (one "M dtype gates angle flips variant" line per key) if
+// that is set.
+
+using TuneKey = std::tuple<int, int, uint32_t, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load()
+{
+    if (g_tune_loaded)
+        return;
+    g_tune_loaded = true;
+    const char *path = getenv("QSIM_TUNE_CACHE");
+    if (path == nullptr || *path == 0)
+        return;
+    FILE *f = fopen(path, "r");
+    if (f == nullptr)
+        return;
+    int M, dt, a, fl, v;
+    unsigned n;
+    while (fscanf(f, "%d %d %u %d %d %d", &M, &dt, &n, &a, &fl, &v) == 6)
+        if (v >= 0 && v < trial_variants())
+            g_tune[TuneKey(M, dt, n, a, fl)] = v;
+    fclose(f);
+}
+
+void tune_store(const TuneKey &k, int v)
+{
+    g_tune[k] = v;
+    const char *path = getenv("QSIM_TUNE_CACHE");
+    if (path == nullptr || *path == 0)
+        return;
+    FILE *f = fopen(path, "a");
+    if (f == nullptr)
+        return;
+    fprintf(f, "%d %d %u %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+            std::get<3>(k), std::get<4>(k), v);
+    fclose(f);
+}
+
+hipError_t launch(int dtype, const TrialLaunch &L, hipStream_t st)
+{
+    return dtype == QSIM_C64 ? launch_trials<float>(L, st) : launch_trials<double>(L, st);
+}
+
+// Time every variant on one round of trials (one trial per workgroup) and
+// keep the fastest.  The timing runs write to a scratch output.
+int autotune(int dtype, TrialLaunch L, hipStream_t st, double *scratch, int &best)
+{
+    best = -1;
+    float best_ms = 0.f;
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess)
+        return hip_err(e, "tune event");
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_err(e, "tune event");
+    }
+    const int elem = dtype == QSIM_C64 ? 8 : 16;
+    for (int v = 0; v < trial_variants(); ++v) {
+        const int grid = trial_grid(v, (int)L.M, elem);
+        if (grid <= 0)
+            continue;
+        L.variant = v;
+        L.grid = grid;
+        L.n_trials = (uint64_t)grid;
+        L.out_F = scratch;
+        // once to warm up, once timed
+        e = launch(dtype, L, st);
+        if (e == hipSuccess)
+            e = hipEventRecord(a, st);
+        if (e == hipSuccess)
+            e = launch(dtype, L, st);
+        if (e == hipSuccess)
+            e = hipEventRecord(b, st);
+        if (e == hipSuccess)
+            e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, a, b);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        if (best < 0 || ms < best_ms) {
+            best = v;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (best < 0)
+        return set_error(QSIM_EDEVICE, "no trial kernel variant could run this register");
+    return QSIM_OK;
+}
+
+}  // namespace
+
+extern "C" int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits, int dtype,
+                               const qsim_error_model *base, uint64_t n_trials, double *out_F)
+{
+    if (dtype != QSIM_C64 && dtype != QSIM_C128)
+        return set_error(QSIM_EINVAL, "dtype %d is neither QSIM_C64 nor QSIM_C128", dtype);
+    const int max_m = dtype == QSIM_C64 ? 14 : 13;
+    if (num_qubits < 1 || num_qubits > max_m)
+        return set_error(QSIM_EINVAL,
+                         "num_qubits %d outside [1, %d]: a trial's register must fit the "
+                         "workgroup's LDS", num_qubits, max_m);
+    if (base == nullptr || !error_model_valid(*base))
+        return set_error(QSIM_EINVAL, "error model missing or invalid");
+    if (n_trials > 0 && out_F == nullptr)
+        return set_error(QSIM_EINVAL, "out_F is NULL");
+    if (n > 0 && gates == nullptr)
+        return set_error(QSIM_EINVAL, "gates is NULL");
+    if (n > (size_t)UINT32_MAX)
+        return set_error(QSIM_EINVAL, "too many gates");
+    char why[160];
+    for (size_t k = 0; k < n; ++k)
+        if (!gate_valid(gates[k], num_qubits, why, sizeof(why)))
+            return set_error(QSIM_EINVAL, "gate %zu: %s", k, why);
+    if (n_trials == 0)
+        return QSIM_OK;
+
+    int device = 0;
+    if (const char *d = getenv("QSIM_DEVICE"))
+        device = atoi(d);
+    qsim_options o{};
+    o.device = device;
+    o.renorm_period = -1;
+    StateGuard ideal;
+    int rc = qsim_create(num_qubits, dtype, &o, &ideal.s);
+    if (rc != QSIM_OK)
+        return rc;
+    rc = qsim_apply_circuit(ideal.s, gates, n);
+    if (rc != QSIM_OK)
+        return rc;
+    rc = qsim_synchronize(ideal.s);
+    if (rc != QSIM_OK)
+        return rc;
+    void *ideal_ptr = nullptr;
+    rc = qsim_info(ideal.s, nullptr, nullptr, nullptr, &ideal_ptr, nullptr);
+    if (rc != QSIM_OK)
+        return rc;
+
+    std::vector<TrialGate> hg(n);
+    for (size_t k = 0; k < n; ++k) {
+        TrialGate t{};
+        t.kind = gates[k].kind;
+        t.target = (uint32_t)gates[k].target;
+        t.cmask = 0;
+        if (gates[k].ctrl0 >= 0)
+            t.cmask |= 1u << gates[k].ctrl0;
+        if (gates[k].ctrl1 >= 0)
+            t.cmask |= 1u << gates[k].ctrl1;
+        t.theta = gates[k].theta;
+        hg[k] = t;
+    }
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess)
+        return hip_err(e, "hipSetDevice");
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess)
+        return hip_err(e, "stream");
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } sg{st};
+    DevBuf dg, dout, dscratch;
+    if ((e = hipMalloc(&dg.p, std::max<size_t>(1, n) * sizeof(TrialGate))) != hipSuccess)
+        return hip_err(e, "gate buffer");
+    if ((e = hipMalloc(&dout.p, n_trials * sizeof(double))) != hipSuccess)
+        return hip_err(e, "output buffer");
+    if (n > 0 && (e = hipMemcpyAsync(dg.p, hg.data(), n * sizeof(TrialGate),
+                                     hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_err(e, "gate upload");
+
+    TrialLaunch L{};
+    L.gates = reinterpret_cast<const TrialGate *>(dg.p);
+    L.ngates = (uint32_t)n;
+    L.M = (uint32_t)num_qubits;
+    L.sigma = base->sigma;
+    L.p_bit = base->p_bitflip;
+    L.p_phase = base->p_phaseflip;
+    L.seed = base->seed;
+    L.trial0 = base->trial;
+    L.ideal = ideal_ptr;
+
+    const TuneKey key(num_qubits, dtype, (uint32_t)n, base->sigma > 0.0 ? 1 : 0,
+                      (base->p_bitflip > 0.0 || base->p_phaseflip > 0.0) ? 1 : 0);
+    int variant = -1;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end())
+            variant = it->second;
+    }
+    const int elem = dtype == QSIM_C64 ? 8 : 16;
+    if (variant < 0 || trial_grid(variant, num_qubits, elem) <= 0) {
+        if ((e = hipMalloc(&dscratch.p, 4096 * sizeof(double))) != hipSuccess)
+            return hip_err(e, "tune buffer");
+        TrialLaunch T = L;
+        T.n_trials = 1;  // grid set per variant inside
+        rc = autotune(dtype, T, st, reinterpret_cast<double *>(dscratch.p), variant);
+        if (rc != QSIM_OK)
+            return rc;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_store(key, variant);
+    }
+    L.variant = variant;
+    L.grid = trial_grid(variant, num_qubits, elem);
+    if (L.grid <= 0)
+        return set_error(QSIM_EDEVICE, "trial kernel cannot run this register");
+    L.n_trials = n_trials;
+    L.out_F = reinterpret_cast<double *>(dout.p);
+    if ((e = launch(dtype, L, st)) != hipSuccess)
+        return hip_err(e, "trial launch");
+    if ((e = hipMemcpyAsync(out_F, dout.p, n_trials * sizeof(double), hipMemcpyDeviceToHost,
+                            st)) != hipSuccess)
+        return hip_err(e, "result copy");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_err(e, "trial sync");
+    return QSIM_OK;
+}
+

@@ -1,0 +1,95 @@
+"""Batched Monte Carlo trials (one persistent launch) against the oracle and
+against the per-register path, through the C-ABI."""
+import numpy as np
+import pytest
+
+import circuitgen as cg
+import oracle
+import paper_quant_ph_9804039_amd as q
+
+pytestmark = pytest.mark.gpu
+
+
+def _single(M, dtype, gates, sigma, p, seed, trial):
+    with q.State(M, dtype, q.make_options(renorm_period=-1)) as ideal, \
+            q.State(M, dtype, q.make_options(renorm_period=-1)) as noisy:
+        ideal.apply(gates)
+        noisy.inject_errors(sigma, p, p, seed=seed, trial=trial)
+        noisy.apply(gates)
+        return ideal.fidelity(noisy)
+
+
+@pytest.mark.parametrize("dtype,tol", [(q.QSIM_C128, 1e-12), (q.QSIM_C64, 1e-6)])
+def test_trials_match_oracle_with_many_flips(dtype, tol):
+    M, G, T = 9, 120, 24
+    gates = cg.random_circuit(M, G, 77, kinds=(cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT, cg.TOFFOLI))
+    em = oracle.Errors(sigma=0.05, p_bitflip=0.01, p_phaseflip=0.01, seed=91, trial=1000)
+    want = oracle.run_trials(gates, M, em, T)
+    got = q.qsim_run_trials(gates, M, dtype, em.sigma, em.p_bitflip, em.p_phaseflip, em.seed,
+                            em.trial, T)
+    assert np.max(np.abs(got - want)) < tol, np.max(np.abs(got - want))
+    # the draws produced real flips in most trials (F far from the angle-only value)
+    assert np.mean(want < 0.9) > 0.3
+
+
+def test_trial_equals_per_register_path():
+    M, G = 12, 200
+    gates = cg.random_circuit(M, G, 12)
+    got = q.qsim_run_trials(gates, M, q.QSIM_C128, 0.01, 2e-3, 2e-3, 5, 40, 6)
+    for t in range(6):
+        F = _single(M, q.QSIM_C128, gates, 0.01, 2e-3, 5, 40 + t)
+        assert abs(got[t] - F) < 1e-12
+
+
+def test_config3_shape_m14_c64_sample_against_oracle():
+    """M=14, 500 gates, sigma=1e-3, p=1e-4 (complex64 state, FP64 reductions):
+    a sample of the batch checked trial by trial against the FP64 oracle."""
+    M, G = 14, 500
+    gates = cg.random_circuit(M, G, 14)
+    em = oracle.Errors(sigma=1e-3, p_bitflip=1e-4, p_phaseflip=1e-4, seed=1014, trial=0)
+    got = q.qsim_run_trials(gates, M, q.QSIM_C64, em.sigma, em.p_bitflip, em.p_phaseflip,
+                            em.seed, 0, 512)
+    want = oracle.run_trials(gates, M, em, 8)
+    assert np.max(np.abs(got[:8] - want)) < 1e-6
+    assert np.all((got >= -1e-6) & (got <= 1 + 1e-6))
+    # trials without any flip keep F close to 1 - O(G sigma^2)
+    flip_free = [t for t in range(8)
+                 if all(oracle.flip_events(oracle.Errors(1e-3, 1e-4, 1e-4, 1014, t), s, qb) == 0
+                        for s in range(G) for qb in range(M))]
+    for t in flip_free:
+        assert got[t] > 0.99
+
+
+def test_error_free_trials_have_unit_fidelity():
+    M = 10
+    gates = cg.random_circuit(M, 100, 3)
+    F = q.qsim_run_trials(gates, M, q.QSIM_C64, 0.0, 0.0, 0.0, 1, 0, 300)
+    assert np.max(np.abs(F - 1.0)) < 1e-6
+    F = q.qsim_run_trials(gates, M, q.QSIM_C128, 0.0, 0.0, 0.0, 1, 0, 10)
+    assert np.max(np.abs(F - 1.0)) < 1e-13
+
+
+def test_trials_deterministic_and_small_registers():
+    for M in (1, 2, 3, 5):
+        kinds = (cg.H, cg.RZ, cg.X, cg.Z) + ((cg.CNOT,) if M >= 2 else ()) + \
+            ((cg.TOFFOLI,) if M >= 3 else ())
+        gates = cg.random_circuit(M, 50, M, kinds=kinds)
+        em = oracle.Errors(sigma=0.1, p_bitflip=0.02, p_phaseflip=0.02, seed=M, trial=7)
+        a = q.qsim_run_trials(gates, M, q.QSIM_C128, 0.1, 0.02, 0.02, M, 7, 20)
+        b = q.qsim_run_trials(gates, M, q.QSIM_C128, 0.1, 0.02, 0.02, M, 7, 20)
+        assert np.array_equal(a, b)
+        want = oracle.run_trials(gates, M, em, 20)
+        assert np.max(np.abs(a - want)) < 1e-12
+
+
+def test_trials_reject_bad_input():
+    g = cg.random_circuit(6, 10, 1)
+    with pytest.raises(q.QsimError):
+        q.qsim_run_trials(g, 15, q.QSIM_C64, 0.1, 0, 0, 0, 0, 4)
+    with pytest.raises(q.QsimError):
+        q.qsim_run_trials(g, 14, q.QSIM_C128, 0.1, 0, 0, 0, 0, 4)
+    with pytest.raises(q.QsimError):
+        q.qsim_run_trials(g, 6, q.QSIM_C64, -0.1, 0, 0, 0, 0, 4)
+    with pytest.raises(q.QsimError):
+        q.qsim_run_trials(cg.gates_from_list([(cg.CNOT, 1, 1)]), 6, q.QSIM_C64, 0.1, 0, 0, 0, 0, 4)
+    assert len(q.qsim_run_trials(g, 6, q.QSIM_C64, 0.1, 0, 0, 0, 0, 0)) == 0
