@@ -221,6 +221,54 @@ int qsim_plan(int num_qubits, int dtype, const qsim_options *opt, const qsim_gat
               size_t n_gates, const qsim_error_model *em, uint64_t step0, qsim_pass_info *out,
               size_t out_cap, size_t *n_passes, size_t *n_ops);
 
+/* ---------------------------------------------------------------- serving
+ *
+ * A request is one simulation: the error-free run and one noisy run of a
+ * circuit on a fresh register, scored by their fidelity (Sec. 1.0: errors
+ * injected at each step, their accumulation tracked).  qsim_serve runs a
+ * stream of requests with continuous batching: requests arrive over time,
+ * each is admitted as soon as a slot (a HIP stream) and room in the HBM
+ * budget for its two registers are free, its work is queued on its slot at
+ * once so that admitted requests run concurrently on the device, and its
+ * registers stay resident until its fidelity has come back, when slot and
+ * memory go to the next waiting request.  All device memory is taken once at
+ * the start; the loop itself never allocates or frees.  Results do not
+ * depend on the mix: a request computes the same fidelity alone and among
+ * others (same kernels, fixed reduction order). */
+typedef struct {
+    int num_qubits;
+    int dtype;
+    const qsim_gate *gates;     /* borrowed for the call */
+    size_t n_gates;
+    qsim_error_model errors;    /* the noisy run's error model */
+    double arrival_s;           /* arrival, seconds after the call starts (>= 0) */
+} qsim_request;
+
+typedef struct {
+    double fidelity;            /* F(error-free, noisy) */
+    double admit_s;             /* admission time, seconds after the call starts */
+    double done_s;              /* time its result was seen complete */
+    int status;                 /* QSIM_OK, or QSIM_ENOMEM if its registers can never
+                                   fit the budget, or the error that stopped it */
+    int slot;                   /* slot it ran on (-1 if never admitted) */
+} qsim_result;
+
+typedef struct {
+    int device;
+    int max_slots;              /* concurrent requests, 1..64; 0: 8 */
+    size_t hbm_budget;          /* bytes for resident registers; 0: the smaller of
+                                   64 GiB and 80% of the free device memory */
+    int strict_fifo;            /* 1: admit in arrival order only; 0: a request
+                                   that fits may pass a waiting one that does not */
+} qsim_serve_options;
+
+/* Serve reqs[0..n) and write out[0..n) (same order).  Blocks until every
+ * request has finished.  EINVAL (nothing run) for a malformed request (bad
+ * M, dtype, gate or error model, negative or non-finite arrival) or options;
+ * ENOMEM if the budget cannot be allocated. */
+int qsim_serve(const qsim_request *reqs, size_t n, const qsim_serve_options *opt,
+               qsim_result *out);
+
 /* Wait for all work queued on the state's stream. */
 int qsim_synchronize(qsim_state *s);
 

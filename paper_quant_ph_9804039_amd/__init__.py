@@ -32,7 +32,7 @@ EXPORTED = [
     "qsim_create", "qsim_destroy", "qsim_reset", "qsim_apply_circuit", "qsim_apply_inverse",
     "qsim_inject_errors", "qsim_fidelity", "qsim_overlap", "qsim_norm", "qsim_probs",
     "qsim_get_amplitudes", "qsim_set_amplitudes", "qsim_run_trials", "qsim_synchronize",
-    "qsim_info", "qsim_profile", "qsim_get_stats", "qsim_last_error", "qsim_plan",
+    "qsim_info", "qsim_profile", "qsim_get_stats", "qsim_last_error", "qsim_plan", "qsim_serve",
 ]
 
 
@@ -77,6 +77,22 @@ class qsim_pass_info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
 
 
+class qsim_request(ctypes.Structure):
+    _fields_ = [("num_qubits", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("gates", ctypes.c_void_p), ("n_gates", ctypes.c_size_t),
+                ("errors", qsim_error_model), ("arrival_s", ctypes.c_double)]
+
+
+class qsim_result(ctypes.Structure):
+    _fields_ = [("fidelity", ctypes.c_double), ("admit_s", ctypes.c_double),
+                ("done_s", ctypes.c_double), ("status", ctypes.c_int), ("slot", ctypes.c_int)]
+
+
+class qsim_serve_options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("max_slots", ctypes.c_int),
+                ("hbm_budget", ctypes.c_size_t), ("strict_fifo", ctypes.c_int)]
+
+
 _lib = None
 
 
@@ -113,6 +129,8 @@ def lib() -> ctypes.CDLL:
         "qsim_plan": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(qsim_options), vp, sz,
                       ctypes.POINTER(qsim_error_model), u64, ctypes.POINTER(qsim_pass_info), sz,
                       ctypes.POINTER(sz), ctypes.POINTER(sz)],
+        "qsim_serve": [ctypes.POINTER(qsim_request), sz, ctypes.POINTER(qsim_serve_options),
+                       ctypes.POINTER(qsim_result)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -275,6 +293,28 @@ def qsim_plan(num_qubits: int, dtype: int, gates, options: qsim_options | None =
                        g.ctypes.data, len(g), ctypes.byref(em) if em else None, step0, out,
                        npass.value, ctypes.byref(npass), ctypes.byref(nops)))
     return [out[i].as_dict() for i in range(npass.value)], nops.value
+
+
+def qsim_serve(requests, max_slots: int = 8, hbm_budget: int = 0, strict_fifo: bool = False,
+               device: int = 0):
+    """Serve a list of requests (dicts with keys M, dtype, gates, sigma,
+    p_bitflip, p_phaseflip, seed, trial, arrival_s) with continuous batching;
+    returns one result dict per request (fidelity, admit_s, done_s, status,
+    slot)."""
+    n = len(requests)
+    arr = (qsim_request * max(1, n))()
+    keep = []
+    for i, r in enumerate(requests):
+        g = _gates(r["gates"])
+        keep.append(g)
+        arr[i] = qsim_request(int(r["M"]), int(r.get("dtype", QSIM_C64)), g.ctypes.data, len(g),
+                              _em(r.get("sigma", 0.0), r.get("p_bitflip", 0.0),
+                                  r.get("p_phaseflip", 0.0), r.get("seed", 0), r.get("trial", 0)),
+                              float(r.get("arrival_s", 0.0)))
+    out = (qsim_result * max(1, n))()
+    opt = qsim_serve_options(device, max_slots, hbm_budget, 1 if strict_fifo else 0)
+    _check(lib().qsim_serve(arr, n, ctypes.byref(opt), out))
+    return [{f: getattr(out[i], f) for f, _ in qsim_result._fields_} for i in range(n)]
 
 
 def qsim_last_error() -> str:

@@ -830,6 +830,82 @@ void release(qsim_state *s)
 
 }  // namespace
 
+// ============================================================ serving slots
+
+namespace qsim {
+
+int slot_state_create(int device, hipStream_t st, int max_qubits, qsim_state **out)
+{
+    *out = nullptr;
+    qsim_state *s = new qsim_state();
+    s->device = device;
+    s->stream = st;
+    s->own_stream = false;
+    s->own_mem = false;
+    const uint64_t tiles = 1ull << std::max(0, max_qubits - 9);  // smallest tile: 9 qubits
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&s->d_partial, 4 * kReduceBlocks * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&s->d_tile_norm, tiles * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&s->d_scalars, 16 * sizeof(double));
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&s->h_pinned, 16 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        const int rc = hip_fail(e, "slot state");
+        release(s);
+        return rc;
+    }
+    *out = s;
+    return QSIM_OK;
+}
+
+int slot_state_bind(qsim_state *s, int num_qubits, int dtype, void *psi)
+{
+    qsim_options o{};
+    o.device = s->device;
+    int rc = configure(s, num_qubits, dtype, o);
+    if (rc != QSIM_OK)
+        return rc;
+    s->psi = psi;
+    s->step = 0;
+    s->armed = false;
+    HIP_TRY(dtype == QSIM_C64
+                ? launch_init_basis<float>((cplx<float> *)psi, num_qubits, 0, s->stream)
+                : launch_init_basis<double>((cplx<double> *)psi, num_qubits, 0, s->stream),
+            "init launch");
+    return QSIM_OK;
+}
+
+int overlap_enqueue(const qsim_state *a, const qsim_state *b, double *host_out4)
+{
+    hipError_t e;
+    if (a->dtype == QSIM_C64 && b->dtype == QSIM_C64)
+        e = launch_overlap<float, float>((const cplx<float> *)a->psi, (const cplx<float> *)b->psi,
+                                         a->M, a->d_partial, a->d_scalars, a->stream);
+    else if (a->dtype == QSIM_C64)
+        e = launch_overlap<float, double>((const cplx<float> *)a->psi,
+                                          (const cplx<double> *)b->psi, a->M, a->d_partial,
+                                          a->d_scalars, a->stream);
+    else if (b->dtype == QSIM_C64)
+        e = launch_overlap<double, float>((const cplx<double> *)a->psi,
+                                          (const cplx<float> *)b->psi, a->M, a->d_partial,
+                                          a->d_scalars, a->stream);
+    else
+        e = launch_overlap<double, double>((const cplx<double> *)a->psi,
+                                           (const cplx<double> *)b->psi, a->M, a->d_partial,
+                                           a->d_scalars, a->stream);
+    HIP_TRY(e, "overlap launch");
+    HIP_TRY(hipMemcpyAsync(host_out4, a->d_scalars, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                           a->stream), "overlap copy");
+    return QSIM_OK;
+}
+
+void slot_state_destroy(qsim_state *s) { release(s); }
+
+}  // namespace qsim
+
 // ===================================================================== C ABI
 
 extern "C" {

@@ -1,6 +1,8 @@
 // Helpers the C-ABI entry points share across source files.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstddef>
 
 #include "qsim.h"
@@ -16,5 +18,15 @@ bool gate_valid(const qsim_gate &g, int M, char *why, size_t n);
 
 // sigma finite and >= 0, both p in [0, 1].
 bool error_model_valid(const qsim_error_model &em);
+
+// Serving slots: a state whose scratch buffers fit registers of up to
+// max_qubits, on a borrowed stream, rebound to borrowed memory per request
+// (so the serving loop never allocates or frees on its hot path).
+int slot_state_create(int device, hipStream_t st, int max_qubits, qsim_state **out);
+int slot_state_bind(qsim_state *s, int num_qubits, int dtype, void *psi);
+void slot_state_destroy(qsim_state *s);
+// Enqueue <a|b>, <a|a>, <b|b> on a's stream and an async copy of the four
+// doubles to pinned host memory (no synchronisation).
+int overlap_enqueue(const qsim_state *a, const qsim_state *b, double *host_out4);
 
 }  // namespace qsim
