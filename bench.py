@@ -15,8 +15,10 @@ scalar fidelity and the 1024 probabilities).
 
 Prints one JSON line.  Extra figures: the same circuit on the one-pass-per-
 gate path, the roofline of the fused tile pass (HIP events around each
-launch, algorithmic bytes 2 x 8 x 2^30 per launch), and the FP64 oracle
-timed on a bounded sample on the host cores.
+launch, algorithmic bytes 2 x 8 x 2^30 per launch), the FP64 oracle timed on
+a bounded sample on the host cores, batched Monte Carlo trials/s (M=14, 500
+gates, 4096 trials, one launch), and the serving loop's p50/p99 latency and
+throughput on a Poisson trace against the same trace served sequentially.
 """
 from __future__ import annotations
 
@@ -80,13 +82,79 @@ def cpu_baseline(gates, budget_s: float = 15.0, max_gates: int = 200):
                       f"{dt:.1f} s on the host"}
 
 
+def bench_mc(q, cg, np):
+    """Batched Monte Carlo: 4096 trials of one M=14, 500-gate circuit in one
+    persistent launch (complex64 registers, FP64 fidelity)."""
+    Mm, Gm, T = 14, 500, 4096
+    gates = cg.random_circuit(Mm, Gm, 14)
+    q.qsim_run_trials(gates, Mm, q.QSIM_C64, SIGMA, P_FLIP, P_FLIP, 1014, 0, 256)  # tune
+    reps = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        F = q.qsim_run_trials(gates, Mm, q.QSIM_C64, SIGMA, P_FLIP, P_FLIP, 1014, 0, T)
+        reps.append(time.perf_counter() - t0)
+    dt = float(np.median(reps))
+    hist, edges = np.histogram(F, bins=10, range=(0.0, 1.0))
+    return {"value": T / dt, "unit": "trials/s", "trials": T, "num_qubits": Mm, "gates": Gm,
+            "ms": dt * 1e3, "fidelity_mean": float(F.mean()), "fidelity_var": float(F.var()),
+            "fidelity_hist_10bins": hist.tolist()}
+
+
+def bench_serving(q, cg, np, n_req: int = 80):
+    """Poisson request stream (M in [10, 28], 100-2000 gates, sigma in
+    {1e-4, 1e-3, 1e-2}, complex64): continuous batching against the same
+    trace served one request at a time."""
+    trace = cg.poisson_trace(n_req, 0.0, 4000)
+    reqs = [{"M": r["M"], "dtype": q.QSIM_C64,
+             "gates": cg.random_circuit(r["M"], r["G"], r["circuit_seed"]),
+             "sigma": r["sigma"], "seed": r["error_seed"], "arrival_s": 0.0} for r in trace]
+    q.qsim_serve(reqs[:4], max_slots=2)  # warm-up
+    t0 = time.perf_counter()
+    q.qsim_serve(reqs, max_slots=1, strict_fifo=True)
+    t_seq = time.perf_counter() - t0
+    rate = 0.8 * n_req / t_seq
+    arrivals = cg.poisson_trace(n_req, rate, 4001)
+    for r, a in zip(reqs, arrivals):
+        r["arrival_s"] = a["t"]
+
+    def summary(res):
+        lat = np.array([x["done_s"] - r["arrival_s"] for r, x in zip(reqs, res)])
+        span = max(x["done_s"] for x in res) - min(r["arrival_s"] for r in reqs)
+        upd = sum(2.0 * len(r["gates"]) * float(1 << r["M"]) for r in reqs)
+        return {"p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "requests_per_s": n_req / span, "amplitude_updates_per_s": upd / span}
+
+    batched = summary(q.qsim_serve(reqs, max_slots=8))
+    sequential = summary(q.qsim_serve(reqs, max_slots=1, strict_fifo=True))
+    return {"requests": n_req, "offered_rate_per_s": rate,
+            "sequential_capacity_per_s": n_req / t_seq,
+            "continuous_batching": batched, "sequential": sequential}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-extra", action="store_true",
+                    help="time the M=30 step only (for counter runs under a profiler)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 4 GiB device-to-device copy 5 times (the known-size "
+                         "kernel the HBM byte counters are scaled by) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        torch.cuda.set_device(0)
+        n = 1 << 30  # 4 GiB of float32
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
+        return 0
     if args.gpus != 1:
         print("bench.py: this build runs one register on one GPU; --gpus must be 1 "
               "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
@@ -143,6 +211,10 @@ def main() -> int:
     traffic = measured_traffic()
     log(f"bench: {value:.3e} amp-upd/s, fused pass {avg_ms:.3f} ms avg, {achieved:.0f} GB/s")
 
+    if args.skip_extra:
+        print(json.dumps({"value": value, "avg_launch_ms": avg_ms, "achieved_GBps": achieved}))
+        return 0
+
     # the same circuit through the one-pass-per-gate path (context)
     plain = q.State(M, q.QSIM_C64, q.torch_options(stream=stream, exec_mode=1, renorm_period=64))
     plain.apply(gates[:20])
@@ -163,13 +235,21 @@ def main() -> int:
     del ideal, noisy
     torch.cuda.empty_cache()
 
+    log("bench: batched Monte Carlo")
+    mc = bench_mc(q, cg, np)
+    log(f"bench: {mc['value']:.0f} trials/s")
+    log("bench: serving")
+    serving = bench_serving(q, cg, np)
+    log(f"bench: serving p99 {serving['continuous_batching']['p99_ms']:.1f} ms "
+        f"(sequential {serving['sequential']['p99_ms']:.1f} ms)")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: oracle sample on the host")
         cpu = cpu_baseline(gates)
 
     out = {
-        "metric": "amplitude-updates/s at M=30 (fused path, error-free + noisy run per step)",
+        "metric": "amplitude-updates/s & % HBM BW at M=30; MC trials/s at M=14; p99 latency",
         "value": value,
         "unit": "amplitude-updates/s",
         "n_gpus": 1,
@@ -198,6 +278,8 @@ def main() -> int:
             "flips_injected": st_n["flips"],
             "per_gate_path": {"value": plain_value, "unit": "amplitude-updates/s",
                               "algorithmic_GBps": plain_gbs, "gates": 200},
+            "mc_trials": mc,
+            "serving": serving,
         },
     }
     print(json.dumps(out), flush=True)
