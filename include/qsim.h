@@ -100,7 +100,10 @@ typedef struct {
     int renorm_period;   /* rescale to unit norm after every R gates.
                             0: default (64 for QSIM_C64, never for QSIM_C128);
                             -1: never */
-    int exec_mode;       /* 0: fused passes (default); 1: one pass per gate */
+    int exec_mode;       /* 0: fused passes, commuting operations reordered so
+                            that a pass carries more of them (default);
+                            1: one pass per operation, in stream order;
+                            2: fused passes over runs of the stream, in order */
     int tile_bits;       /* qubits per fused tile, 9..14; 0: default (13 for
                             QSIM_C64, 12 for QSIM_C128) */
     int low_bits;        /* low qubits always in a fused tile, 1..tile_bits-1;
@@ -198,8 +201,7 @@ int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits, int dtype,
 typedef struct {
     uint32_t fused;      /* 1: tile pass (one HBM read + write for all its
                             operations); 0: one whole-vector pass per operation */
-    uint32_t first_op;   /* index into the lowered operation stream (gates plus
-                            injected flips, in order) */
+    uint32_t first_op;   /* index into the execution order (see op_order) */
     uint32_t n_ops;
     uint32_t n_groups;   /* register groups inside a tile pass */
     uint32_t norm_after; /* 1: a renormalisation follows this pass */
@@ -209,17 +211,21 @@ typedef struct {
 
 /* Host-only dry run of qsim_apply_circuit for a register created with
  * (num_qubits, dtype, opt): lower the gates (drawing the errors of em, NULL =
- * none, starting at step0), partition the operation stream into passes the
+ * none, starting at step0) into the operation stream (each gate, then its
+ * step's flips), fix the execution order and partition it into passes the
  * way the library would (Sec. 2.1: a gate only mixes the amplitude pairs of
- * its target, so a run of gates whose targets lie in one set of qubits can
- * be applied tile by tile in one pass over the state), and check every pass's
- * kernel arguments for consistency.  Writes min(out_cap, passes) entries of
- * out (may be NULL), and the pass and operation counts.  No device is used.
- * EINVAL for bad arguments; EDEVICE if a pass fails its own consistency
- * check (a library bug). */
+ * its target, so gates whose targets lie in one set of qubits can be applied
+ * tile by tile in one pass over the state; commuting operations may be
+ * reordered for that), and check every pass's kernel arguments for
+ * consistency.  Writes min(out_cap, passes) entries of out, and
+ * min(order_cap, operations) entries of op_order (op_order[i] = stream index
+ * of the i-th operation executed); either may be NULL.  Also the pass and
+ * operation counts.  No device is used.  EINVAL for bad arguments; EDEVICE if
+ * a pass fails its own consistency check (a library bug). */
 int qsim_plan(int num_qubits, int dtype, const qsim_options *opt, const qsim_gate *gates,
               size_t n_gates, const qsim_error_model *em, uint64_t step0, qsim_pass_info *out,
-              size_t out_cap, size_t *n_passes, size_t *n_ops);
+              size_t out_cap, size_t *n_passes, size_t *n_ops, uint32_t *op_order,
+              size_t order_cap);
 
 /* ---------------------------------------------------------------- serving
  *

@@ -128,7 +128,7 @@ def lib() -> ctypes.CDLL:
         "qsim_get_stats": [vp, ctypes.POINTER(qsim_stats)],
         "qsim_plan": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(qsim_options), vp, sz,
                       ctypes.POINTER(qsim_error_model), u64, ctypes.POINTER(qsim_pass_info), sz,
-                      ctypes.POINTER(sz), ctypes.POINTER(sz)],
+                      ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_uint32), sz],
         "qsim_serve": [ctypes.POINTER(qsim_request), sz, ctypes.POINTER(qsim_serve_options),
                        ctypes.POINTER(qsim_result)],
     }
@@ -279,20 +279,28 @@ def qsim_get_stats(h) -> dict:
 
 
 def qsim_plan(num_qubits: int, dtype: int, gates, options: qsim_options | None = None,
-              sigma=None, p_bitflip=0.0, p_phaseflip=0.0, seed=0, trial=0, step0: int = 0):
-    """Host-only dry run of the pass schedule: (list of pass dicts, op count)."""
+              sigma=None, p_bitflip=0.0, p_phaseflip=0.0, seed=0, trial=0, step0: int = 0,
+              return_order: bool = False):
+    """Host-only dry run of the pass schedule: (list of pass dicts, op count),
+    plus the execution order (stream index of each executed operation) when
+    return_order is set."""
     g = _gates(gates)
     em = None if sigma is None else _em(sigma, p_bitflip, p_phaseflip, seed, trial)
     npass, nops = ctypes.c_size_t(), ctypes.c_size_t()
     L = lib()
-    _check(L.qsim_plan(num_qubits, dtype, ctypes.byref(options) if options else None,
-                       g.ctypes.data, len(g), ctypes.byref(em) if em else None, step0, None, 0,
-                       ctypes.byref(npass), ctypes.byref(nops)))
+    opt = ctypes.byref(options) if options else None
+    emp = ctypes.byref(em) if em else None
+    _check(L.qsim_plan(num_qubits, dtype, opt, g.ctypes.data, len(g), emp, step0, None, 0,
+                       ctypes.byref(npass), ctypes.byref(nops), None, 0))
     out = (qsim_pass_info * max(1, npass.value))()
-    _check(L.qsim_plan(num_qubits, dtype, ctypes.byref(options) if options else None,
-                       g.ctypes.data, len(g), ctypes.byref(em) if em else None, step0, out,
-                       npass.value, ctypes.byref(npass), ctypes.byref(nops)))
-    return [out[i].as_dict() for i in range(npass.value)], nops.value
+    order = np.zeros(max(1, nops.value), dtype=np.uint32)
+    _check(L.qsim_plan(num_qubits, dtype, opt, g.ctypes.data, len(g), emp, step0, out,
+                       npass.value, ctypes.byref(npass), ctypes.byref(nops),
+                       order.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), nops.value))
+    passes = [out[i].as_dict() for i in range(npass.value)]
+    if return_order:
+        return passes, nops.value, order[:nops.value]
+    return passes, nops.value
 
 
 def qsim_serve(requests, max_slots: int = 8, hbm_budget: int = 0, strict_fifo: bool = False,

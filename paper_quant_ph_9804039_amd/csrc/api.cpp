@@ -400,53 +400,125 @@ bool tile_shape(const qsim_state *s, int &k, int &G)
     return G >= 3 && G <= 5;
 }
 
-// Greedy, order-preserving partition into passes.  A fused pass starts with
-// the low qubits in its tile set and adds the target of each next
-// non-diagonal operation until the set holds k qubits; diagonal operations
-// never constrain it.  A pass also ends at a renormalisation boundary.
-void schedule(const qsim_state *s, const std::vector<Op> &ops, std::vector<PassPlan> &plan)
+// Qubits an operation acts on as the target of a non-diagonal transform
+// (x), and as a control or the target of a diagonal one (z).  Two operations
+// commute when neither one's x qubits meet the other's x or z qubits: they
+// then act on disjoint qubits, or share only qubits on which both are
+// diagonal in the computational basis.
+struct OpUse {
+    uint64_t x, z;
+};
+
+OpUse op_use(const Op &op)
 {
-    const size_t n = ops.size();
-    int k, G;
-    if (s->exec_mode == 1 || !tile_shape(s, k, G)) {
-        for (size_t i = 0; i < n; ++i)
-            plan.push_back({false, i, 1, renorm_due(s, ops[i])});
-        return;
-    }
+    const uint64_t t = 1ull << op.target;
+    const bool diag = op.type == kOpDiag || op.type == kOpNeg;
+    return {diag ? 0ull : t, op.cmask | (diag ? t : 0ull)};
+}
+
+// Partition ops[lo, hi) into fused passes, appending the operations to
+// `order` pass by pass.  A pass starts with the low qubits in its tile set
+// and scans the operations not yet placed, in stream order: it takes an
+// operation when the operation commutes with every earlier one still left
+// behind and its target is in the tile set or the set has room for it
+// (diagonal operations without controls never constrain the set).  In-order
+// mode stops the scan at the first operation it cannot take instead, so
+// passes are runs of the stream.  Every pass takes at least the first
+// operation left (it commutes with nothing earlier and the set has room).
+void schedule_fused(const qsim_state *s, const std::vector<Op> &ops, size_t lo, size_t hi, int k,
+                    bool reorder, std::vector<uint32_t> &order, std::vector<PassPlan> &plan)
+{
     const int low = std::min(s->low_bits, k);
-    size_t i = 0;
-    while (i < n) {
+    std::vector<uint32_t> rem, left;
+    for (size_t i = lo; i < hi; ++i)
+        rem.push_back((uint32_t)i);
+    while (!rem.empty()) {
         uint64_t S = (low >= 64) ? ~0ull : ((1ull << low) - 1);
         int size = low;
-        size_t j = i;
-        bool norm = false;
-        while (j < n && j - i < (size_t)kMaxPassOps) {
-            const Op &op = ops[j];
-            if (!fusable(op))
-                break;
-            if (needs_tile_target(op)) {
+        uint64_t bx = 0, bz = 0;  // qubits held by operations left behind
+        const size_t first = order.size();
+        size_t taken = 0;
+        left.clear();
+        for (size_t r = 0; r < rem.size(); ++r) {
+            const Op &op = ops[rem[r]];
+            const OpUse u = op_use(op);
+            bool ok = taken < (size_t)kMaxPassOps && (u.x & (bx | bz)) == 0 && (u.z & bx) == 0;
+            if (ok && needs_tile_target(op)) {
                 const uint64_t tb = 1ull << op.target;
                 if (!(S & tb)) {
-                    if (size == k)
-                        break;
-                    S |= tb;
-                    ++size;
+                    if (size == k) {
+                        ok = false;
+                    } else {
+                        S |= tb;
+                        ++size;
+                    }
                 }
             }
-            ++j;
-            if (renorm_due(s, op)) {
-                norm = true;
+            if (ok) {
+                order.push_back(rem[r]);
+                ++taken;
+                continue;
+            }
+            if (!reorder || taken == (size_t)kMaxPassOps) {
+                left.insert(left.end(), rem.begin() + (std::ptrdiff_t)r, rem.end());
                 break;
             }
+            left.push_back(rem[r]);
+            bx |= u.x;
+            bz |= u.z;
         }
-        if (j == i) {
-            // the tile cannot take this target (no free tile qubit): own pass
-            plan.push_back({false, i, 1, renorm_due(s, ops[i])});
-            i = i + 1;
-            continue;
+        plan.push_back({true, first, taken, false});
+        rem.swap(left);
+    }
+}
+
+// Partition the operation stream into passes and fix the order in which the
+// operations run (order[i] = stream index of the i-th operation to run).  An
+// operation a fused pass cannot carry gets a pass of its own, and no
+// operation moves across it.  Plain mode, and registers too small for a
+// tile (M < 9), run one pass per operation in stream order.
+//
+// Renormalisation is a scaling of the whole state, which commutes with every
+// operation, so it does not pin the order: the norm is taken after the first
+// pass by which every operation up to a renormalisation boundary has run
+// (several boundaries may share one), and the next pass applies the scale.
+void schedule(const qsim_state *s, const std::vector<Op> &ops, std::vector<uint32_t> &order,
+              std::vector<PassPlan> &plan)
+{
+    const size_t n = ops.size();
+    order.clear();
+    order.reserve(n);
+    int k, G;
+    if (s->exec_mode == 1 || !tile_shape(s, k, G)) {
+        for (size_t i = 0; i < n; ++i) {
+            order.push_back((uint32_t)i);
+            plan.push_back({false, i, 1, false});
         }
-        plan.push_back({true, i, j - i, norm});
-        i = j;
+    } else {
+        const bool reorder = s->exec_mode == 0;
+        size_t lo = 0;
+        for (size_t i = 0; i < n; ++i) {
+            if (!fusable(ops[i])) {
+                schedule_fused(s, ops, lo, i, k, reorder, order, plan);
+                order.push_back((uint32_t)i);
+                plan.push_back({false, order.size() - 1, 1, false});
+                lo = i + 1;
+            }
+        }
+        schedule_fused(s, ops, lo, n, k, reorder, order, plan);
+    }
+    // renormalisation points
+    std::vector<bool> ran(n, false);
+    size_t prefix = 0;  // every stream index below it has run
+    size_t next = 0;    // next operation to check for a boundary
+    for (PassPlan &p : plan) {
+        for (size_t i = p.first; i < p.first + p.count; ++i)
+            ran[order[i]] = true;
+        while (prefix < n && ran[prefix])
+            ++prefix;
+        for (; next < prefix; ++next)
+            if (renorm_due(s, ops[next]))
+                p.norm_after = true;
     }
 }
 
@@ -671,10 +743,14 @@ bool tile_args_consistent(const TileArgs<R> &A, int G, const std::vector<Op> &op
 }
 
 template <typename R>
-int run_ops(qsim_state *s, const std::vector<Op> &ops)
+int run_ops(qsim_state *s, const std::vector<Op> &stream)
 {
     std::vector<PassPlan> plan;
-    schedule(s, ops, plan);
+    std::vector<uint32_t> order;
+    schedule(s, stream, order, plan);
+    std::vector<Op> ops(order.size());
+    for (size_t i = 0; i < order.size(); ++i)
+        ops[i] = stream[order[i]];
     cplx<R> *psi = reinterpret_cast<cplx<R> *>(s->psi);
     const double full = 2.0 * (double)(1ull << s->M) * (double)elem_bytes(s->dtype);
     bool scale_pending = false;
@@ -762,7 +838,7 @@ int configure(qsim_state *s, int num_qubits, int dtype, const qsim_options &o)
         return fail(QSIM_EINVAL, "num_qubits %d outside [1, %d]", num_qubits, QSIM_MAX_QUBITS);
     if (dtype != QSIM_C64 && dtype != QSIM_C128)
         return fail(QSIM_EINVAL, "dtype %d is neither QSIM_C64 nor QSIM_C128", dtype);
-    if (o.exec_mode != 0 && o.exec_mode != 1)
+    if (o.exec_mode < 0 || o.exec_mode > 2)
         return fail(QSIM_EINVAL, "exec_mode %d", o.exec_mode);
     if (o.renorm_period < -1)
         return fail(QSIM_EINVAL, "renorm_period %d", o.renorm_period);
@@ -1263,7 +1339,8 @@ int qsim_set_amplitudes(qsim_state *s, uint64_t offset, uint64_t count, const do
 
 int qsim_plan(int num_qubits, int dtype, const qsim_options *opt, const qsim_gate *gates,
               size_t n_gates, const qsim_error_model *em, uint64_t step0, qsim_pass_info *out,
-              size_t out_cap, size_t *n_passes, size_t *n_ops)
+              size_t out_cap, size_t *n_passes, size_t *n_ops, uint32_t *op_order,
+              size_t order_cap)
 {
     qsim_options o{};
     if (opt)
@@ -1282,14 +1359,21 @@ int qsim_plan(int num_qubits, int dtype, const qsim_options *opt, const qsim_gat
         st.armed = true;
     }
     st.step = step0;
-    std::vector<Op> ops;
-    lower_circuit(&st, gates, n_gates, ops);
+    std::vector<Op> stream;
+    lower_circuit(&st, gates, n_gates, stream);
     std::vector<PassPlan> plan;
-    schedule(&st, ops, plan);
+    std::vector<uint32_t> order;
+    schedule(&st, stream, order, plan);
+    std::vector<Op> ops(order.size());
+    for (size_t i = 0; i < order.size(); ++i)
+        ops[i] = stream[order[i]];
     if (n_passes)
         *n_passes = plan.size();
     if (n_ops)
         *n_ops = ops.size();
+    if (op_order)
+        for (size_t i = 0; i < order.size() && i < order_cap; ++i)
+            op_order[i] = order[i];
     for (size_t i = 0; i < plan.size(); ++i) {
         qsim_pass_info info{};
         info.fused = plan[i].fused ? 1u : 0u;

@@ -86,11 +86,16 @@ def test_permutation_gates_basis_states_bit_exact(mode, dtype):
 
 
 @pytest.mark.parametrize("mode,group", [(0, 3), (0, 4), (0, 5), (1, 0)])
-def test_permutation_circuit_on_random_state_bit_exact(mode, group):
-    M = 15
-    gates = cg.random_circuit(M, 120, 17, kinds=(cg.X, cg.CNOT, cg.TOFFOLI))
+@pytest.mark.parametrize("M,kinds", [(15, (cg.X, cg.CNOT, cg.TOFFOLI)),
+                                     (15, (cg.X, cg.Z, cg.CNOT, cg.TOFFOLI)),
+                                     (10, (cg.Z, cg.X, cg.TOFFOLI))])
+def test_permutation_circuit_on_random_state_bit_exact(mode, group, M, kinds):
+    # exact X / Z / CNOT / Toffoli only move amplitudes and flip signs, so
+    # every path must reproduce the oracle bit for bit (Z lands on group
+    # bits and off them, in one-tile and many-tile registers)
+    gates = cg.random_circuit(M, 120, 17, kinds=kinds)
     for dtype in (q.QSIM_C64, q.QSIM_C128):
-        shape = {"group_bits": group, "tile_bits": group + 8} if group else {}
+        shape = {"group_bits": min(group, M - 6), "tile_bits": min(group + 8, M)} if group else {}
         with state(M, dtype, exec_mode=mode, renorm_period=-1, **shape) as s:
             v = cg.random_state(M, 3)
             if dtype == q.QSIM_C64:
@@ -308,7 +313,12 @@ def test_renormalisation_keeps_c64_norm():
             a = s.amplitudes()
             assert np.max(np.abs(a - ref)) < 5e-5
             st = s.stats()
-            assert st["renorms"] == 400 // 16
+            # one pass per gate renormalises at every boundary; fused passes
+            # may let one renormalisation cover several boundaries
+            if mode == 1:
+                assert st["renorms"] == 400 // 16
+            else:
+                assert 1 <= st["renorms"] <= 400 // 16
 
 
 def test_invalid_gates_rejected_and_state_untouched():

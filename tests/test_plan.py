@@ -54,8 +54,8 @@ def test_flip_count_matches_oracle_draws():
 
 
 def test_fusion_factor_of_uniform_random_circuit():
-    # targets uniform over 30 qubits: a 13-qubit tile with 5 low qubits holds
-    # runs of about a dozen gates
+    # targets uniform over 30 qubits: a 13-qubit tile with 4 low qubits holds
+    # a dozen or more gates
     gates = cg.random_circuit(30, 1000, 30)
     passes, _ = q.qsim_plan(30, q.QSIM_C64, gates)
     assert all(p["fused"] for p in passes)
@@ -65,7 +65,9 @@ def test_fusion_factor_of_uniform_random_circuit():
 def test_renorm_boundaries_end_passes():
     gates = cg.random_circuit(16, 256, 1)
     passes, _ = q.qsim_plan(16, q.QSIM_C64, gates, q.make_options(renorm_period=32))
-    assert sum(p["norm_after"] for p in passes) == 256 // 32
+    assert 1 <= sum(p["norm_after"] for p in passes) <= 256 // 32
+    perop, _ = q.qsim_plan(16, q.QSIM_C64, gates, q.make_options(renorm_period=32, exec_mode=1))
+    assert [i for i, p in enumerate(perop) if p["norm_after"]] == list(range(31, 256, 32))
     plain, _ = q.qsim_plan(16, q.QSIM_C64, gates, q.make_options(exec_mode=1))
     assert len(plain) == 256 and not any(p["fused"] for p in plain)
 
@@ -87,3 +89,27 @@ def test_plan_rejects_bad_input():
     with pytest.raises(q.QsimError):
         q.qsim_plan(20, q.QSIM_C128, cg.gates_from_list([(cg.H, 1)]),
                     q.make_options(tile_bits=14, group_bits=5))
+
+
+@pytest.mark.parametrize("M,tile,group", [(10, 10, 4), (10, 10, 3), (11, 11, 5), (12, 12, 4),
+                                          (16, 10, 4), (20, 12, 5)])
+def test_control_heavy_passes_keep_group_bits_free(M, tile, group):
+    # Toffoli-dense runs: the controls of a group's operations can cover
+    # most of the tile (qsim_plan checks every pass's arguments)
+    gates = cg.random_circuit(M, 400, 500 + M, kinds=(cg.TOFFOLI, cg.CNOT, cg.H))
+    opt = q.make_options(tile_bits=tile, group_bits=group)
+    passes, nops = q.qsim_plan(M, q.QSIM_C64, gates, opt, sigma=0.01, p_bitflip=0.01,
+                               p_phaseflip=0.01, seed=9, trial=2)
+    assert sum(p["n_ops"] for p in passes) == nops
+    assert any(p["fused"] and p["n_groups"] > 1 for p in passes)
+
+
+def test_toffoli_run_whose_controls_cover_the_tile():
+    # two targets and eight distinct controls: one fused pass whose
+    # arguments pass the builder's own consistency check for every shape
+    T = cg.TOFFOLI
+    gates = cg.gates_from_list([(T, 0, 2, 3), (T, 1, 4, 5), (T, 0, 6, 7), (T, 1, 8, 9)] * 3)
+    for group in (3, 4):
+        opt = q.make_options(tile_bits=10, group_bits=group)
+        passes, nops = q.qsim_plan(10, q.QSIM_C128, gates, opt)
+        assert [p["fused"] for p in passes] == [1] and passes[0]["n_ops"] == nops == 12

@@ -1,0 +1,131 @@
+"""The execution order chosen by the pass scheduler (CPU only, through
+qsim_plan): a permutation of the operation stream that keeps the relative
+order of every two operations that do not commute, never moves an operation
+across a renormalisation boundary, and keeps every fused pass's targets in its
+tile.  The stream and the commutation rule are modelled here from the gates
+and the oracle's flip draws, independently of the library."""
+import numpy as np
+import pytest
+
+import circuitgen as cg
+import oracle
+import paper_quant_ph_9804039_amd as q
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    try:
+        q.lib()
+    except ImportError as e:
+        pytest.skip(str(e))
+
+
+def _stream(gates, M, em):
+    """Per operation [x_qubits, z_qubits, target or None, step, step_end]:
+    x = target of a non-diagonal transform, z = controls and diagonal
+    targets; the target is kept when the operation needs it in the tile
+    (everything but an uncontrolled diagonal)."""
+    ops = []
+    for s, g in enumerate(gates):
+        kind, t = int(g["kind"]), int(g["target"])
+        ctrls = {int(c) for c in (g["ctrl0"], g["ctrl1"]) if c >= 0}
+        diag = kind in (cg.RZ, cg.Z)
+        ops.append([set() if diag else {t}, ctrls | ({t} if diag else set()),
+                    t if (not diag or ctrls) else None, s, True])
+        for qb in range(M):
+            ev = oracle.flip_events(em, s, qb)
+            if ev:
+                ops[-1][4] = False
+            if ev & 1:
+                ops.append([{qb}, set(), qb, s, True])
+            if ev & 2:
+                if ev & 1:
+                    ops[-1][4] = False
+                ops.append([set(), {qb}, None, s, True])
+    return ops
+
+
+def _commute(a, b):
+    return not (a[0] & (b[0] | b[1])) and not (b[0] & (a[0] | a[1]))
+
+
+def _check(M, gates, em, opt, period=0):
+    passes, nops, order = q.qsim_plan(M, q.QSIM_C64, gates, opt, sigma=em.sigma,
+                                      p_bitflip=em.p_bitflip, p_phaseflip=em.p_phaseflip,
+                                      seed=em.seed, trial=em.trial, return_order=True)
+    ops = _stream(gates, M, em)
+    assert nops == len(ops)
+    assert sorted(order.tolist()) == list(range(nops))
+    pos = np.empty(nops, dtype=np.int64)
+    pos[order] = np.arange(nops)
+    for i in range(nops):
+        for j in range(i + 1, nops):
+            if not _commute(ops[i], ops[j]):
+                assert pos[i] < pos[j], (i, j)
+    # renormalisation: the norm follows the first pass by which every
+    # operation up to a boundary (the end of every period-th step) has run
+    if period > 0:
+        want = set()
+        for i, op in enumerate(ops):
+            if op[4] and (op[3] + 1) % period == 0:
+                done_at = pos[: i + 1].max()
+                want.add(next(n for n, p in enumerate(passes)
+                              if p["first_op"] <= done_at < p["first_op"] + p["n_ops"]))
+        assert {n for n, p in enumerate(passes) if p["norm_after"]} == want
+    nxt = 0
+    for p in passes:
+        assert p["first_op"] == nxt
+        nxt += p["n_ops"]
+        if p["fused"]:
+            for i in order[p["first_op"]: p["first_op"] + p["n_ops"]]:
+                if ops[i][2] is not None:
+                    assert (p["tile_mask"] >> ops[i][2]) & 1, (p, i)
+    assert nxt == nops
+    return passes, order, ops
+
+
+@pytest.mark.parametrize("M,seed", [(12, 1), (16, 2), (20, 3), (30, 4)])
+def test_order_keeps_every_non_commuting_pair(M, seed):
+    gates = cg.random_circuit(M, 200, seed, kinds=(cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT, cg.TOFFOLI))
+    em = oracle.Errors(sigma=0.01, p_bitflip=0.01, p_phaseflip=0.01, seed=seed, trial=5)
+    _check(M, gates, em, None)
+
+
+def test_tiles_hold_the_targets_at_full_tile_size():
+    M = 24
+    gates = cg.random_circuit(M, 300, 8)
+    em = oracle.Errors(sigma=1e-3, p_bitflip=1e-3, p_phaseflip=1e-3, seed=8, trial=0)
+    passes, _, _ = _check(M, gates, em, None)
+    assert all(p["fused"] and bin(p["tile_mask"]).count("1") == 13 for p in passes)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_norm_follows_the_pass_that_completes_each_boundary(mode):
+    M = 16
+    gates = cg.random_circuit(M, 256, 11)
+    em = oracle.Errors(sigma=0.0, p_bitflip=0.005, p_phaseflip=0.005, seed=11, trial=2)
+    passes, _, _ = _check(M, gates, em, q.make_options(renorm_period=16, exec_mode=mode),
+                          period=16)
+    assert 1 <= sum(p["norm_after"] for p in passes) <= 256 // 16
+
+
+def test_in_order_mode_runs_the_stream_as_is():
+    M = 20
+    gates = cg.random_circuit(M, 300, 12)
+    passes, nops, order = q.qsim_plan(M, q.QSIM_C64, gates, q.make_options(exec_mode=2),
+                                      return_order=True)
+    assert np.array_equal(order, np.arange(nops))
+    plain, _, order1 = q.qsim_plan(M, q.QSIM_C64, gates, q.make_options(exec_mode=1),
+                                   return_order=True)
+    assert np.array_equal(order1, np.arange(nops)) and len(plain) == nops
+
+
+def test_reordering_cuts_the_passes_of_a_uniform_random_circuit():
+    # targets uniform over 30 qubits: commuting gates from further down the
+    # stream fill each tile, so a third fewer passes than runs of the stream
+    gates = cg.random_circuit(30, 1000, 30)
+    reord, _ = q.qsim_plan(30, q.QSIM_C64, gates)
+    inorder, _ = q.qsim_plan(30, q.QSIM_C64, gates, q.make_options(exec_mode=2))
+    assert all(p["fused"] for p in reord + inorder)
+    assert len(reord) * 1.3 < len(inorder)
+    assert 1000 / len(reord) > 20
