@@ -15,7 +15,8 @@ scalar fidelity and the 1024 probabilities).
 
 Prints one JSON line.  Extra figures: the same circuit on the one-pass-per-
 gate path, the roofline of the fused tile pass (HIP events around each
-launch, algorithmic bytes 2 x 8 x 2^30 per launch), the FP64 oracle timed on
+launch; algorithmic bytes 2 x 8 x 2^30 and algorithmic flops per launch, and
+the ceiling its arithmetic intensity puts it under), the FP64 oracle timed on
 a bounded sample on the host cores, batched Monte Carlo trials/s (M=14, 500
 gates, 4096 trials, one launch), and the serving loop's p50/p99 latency and
 throughput on a Poisson trace against the same trace served sequentially.
@@ -33,6 +34,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# FP32 vector FMA ceiling without packed-FP32 instructions (which this build
+# never emits): 256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz.
+# The published 157.3 TFLOP/s counts packed FP32 (two FMAs per lane).
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 M = 30
 GATES = 1000
 CIRCUIT_SEED = 30
@@ -208,11 +213,19 @@ def main() -> int:
     launch_bytes = 2.0 * 8.0 * float(1 << M)
     avg_ms = fused_ms / max(1, fused_n)
     achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
+    launch_flops = (st_i["fused_flops"] + st_n["fused_flops"]) / max(1, fused_n)
+    achieved_tf = launch_flops / (avg_ms * 1e-3) / 1e12
+    # roofline: the pass is ALU-bound when its arithmetic intensity is past
+    # the ridge point of the two ceilings
+    intensity = launch_flops / launch_bytes
+    ridge = ALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
     traffic = measured_traffic()
-    log(f"bench: {value:.3e} amp-upd/s, fused pass {avg_ms:.3f} ms avg, {achieved:.0f} GB/s")
+    log(f"bench: {value:.3e} amp-upd/s, fused pass {avg_ms:.3f} ms avg, {achieved:.0f} GB/s, "
+        f"{achieved_tf:.1f} TFLOP/s, {intensity:.1f} flop/B (ridge {ridge:.1f})")
 
     if args.skip_extra:
-        print(json.dumps({"value": value, "avg_launch_ms": avg_ms, "achieved_GBps": achieved}))
+        print(json.dumps({"value": value, "avg_launch_ms": avg_ms, "achieved_GBps": achieved,
+                          "achieved_TFLOPs": achieved_tf, "flop_per_byte": intensity}))
         return 0
 
     # the same circuit through the one-pass-per-gate path (context)
@@ -248,6 +261,16 @@ def main() -> int:
         log("bench: oracle sample on the host")
         cpu = cpu_baseline(gates)
 
+    hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS}
+    alu = {"bound": "alu", "achieved": achieved_tf, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": achieved_tf / ALU_PEAK_TFLOPS}
+    roofline = dict(alu if intensity > ridge else hbm)
+    roofline.update({
+        "traffic": traffic, "kernel": "k_tile (fused tile pass)", "launches": fused_n,
+        "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": launch_bytes,
+        "algorithmic_flops_per_launch": launch_flops, "flop_per_byte": intensity,
+        "ridge_flop_per_byte": ridge, "hbm_frac": hbm["frac"], "alu_frac": alu["frac"]})
     out = {
         "metric": "amplitude-updates/s & % HBM BW at M=30; MC trials/s at M=14; p99 latency",
         "value": value,
@@ -267,10 +290,7 @@ def main() -> int:
                    "p_bitflip": P_FLIP, "p_phaseflip": P_FLIP, "renorm_period": 64,
                    "circuit_seed": CIRCUIT_SEED, "error_seed": ERROR_SEED,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_tile (fused tile pass)", "launches": fused_n,
-                     "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": launch_bytes},
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": {
             "fidelity_mean": float(np.mean(Fs)),

@@ -126,6 +126,8 @@ typedef struct {
     double fused_ms;         /* summed duration of the fused launches */
     double fused_bytes;      /* algorithmic HBM bytes of the fused launches */
     double other_ms;         /* reductions, init, scaling */
+    double fused_flops;      /* algorithmic real flops of the fused launches
+                                (see qsim_pass_info.flops) */
 } qsim_stats;
 
 /* Allocate a register of num_qubits (1..QSIM_MAX_QUBITS) in `dtype` and set it
@@ -207,6 +209,12 @@ typedef struct {
     uint32_t norm_after; /* 1: a renormalisation follows this pass */
     uint32_t pad;
     uint64_t tile_mask;  /* qubits spanned by the tile of a fused pass */
+    double flops;        /* algorithmic real flops: per operation, those of its
+                            2x2 on each amplitude it updates (6 for a real 2x2,
+                            a perturbed X or a diagonal phase; 10 for a real
+                            2x2 plus i*w on the diagonal; 0 for a swap or a
+                            sign flip) on the 2^-c of the register that
+                            satisfies its c controls */
 } qsim_pass_info;
 
 /* Host-only dry run of qsim_apply_circuit for a register created with

@@ -61,7 +61,8 @@ class qsim_stats(ctypes.Structure):
                 ("passes", ctypes.c_uint64), ("fused_passes", ctypes.c_uint64),
                 ("renorms", ctypes.c_uint64), ("pass_ms", ctypes.c_double),
                 ("pass_bytes", ctypes.c_double), ("fused_ms", ctypes.c_double),
-                ("fused_bytes", ctypes.c_double), ("other_ms", ctypes.c_double)]
+                ("fused_bytes", ctypes.c_double), ("other_ms", ctypes.c_double),
+                ("fused_flops", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -71,7 +72,7 @@ class qsim_pass_info(ctypes.Structure):
     _fields_ = [("fused", ctypes.c_uint32), ("first_op", ctypes.c_uint32),
                 ("n_ops", ctypes.c_uint32), ("n_groups", ctypes.c_uint32),
                 ("norm_after", ctypes.c_uint32), ("pad", ctypes.c_uint32),
-                ("tile_mask", ctypes.c_uint64)]
+                ("tile_mask", ctypes.c_uint64), ("flops", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}

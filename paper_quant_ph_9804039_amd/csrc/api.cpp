@@ -54,6 +54,7 @@ struct PendingTiming {
     hipEvent_t start, stop;
     int kind;      // 0 plain pass, 1 fused pass, 2 other
     double bytes;
+    double flops;
 };
 
 }  // namespace
@@ -147,6 +148,7 @@ int flush_timings(qsim_state *s)
             if (p.kind == 1) {
                 s->stats.fused_ms += ms;
                 s->stats.fused_bytes += p.bytes;
+                s->stats.fused_flops += p.flops;
             }
             if (p.kind == 2)
                 s->stats.other_ms += ms;
@@ -164,7 +166,9 @@ struct Timed {
     hipEvent_t a = nullptr;
     int kind;
     double bytes;
-    Timed(qsim_state *st, int kd, double by) : s(st), kind(kd), bytes(by)
+    double flops;
+    Timed(qsim_state *st, int kd, double by, double fl = 0.0)
+        : s(st), kind(kd), bytes(by), flops(fl)
     {
         if (s->profiling) {
             a = take_event(s);
@@ -180,7 +184,7 @@ struct Timed {
         if (b == nullptr)
             return;
         (void)hipEventRecord(b, s->stream);
-        s->pending.push_back({a, b, kind, bytes});
+        s->pending.push_back({a, b, kind, bytes, flops});
         if (s->pending.size() > 8192)
             flush_timings(s);
     }
@@ -360,6 +364,22 @@ double plain_bytes(const qsim_state *s, const Op &op)
     if (op.type == kOpNeg)
         frac *= 0.5;
     return full * frac;
+}
+
+// Algorithmic real flops of one operation over a 2^M register: the flops of
+// its 2x2 per amplitude it updates (a real 2x2, or a perturbed X with its
+// zero diagonal: 6; a real 2x2 plus i*w on the diagonal: 10; a diagonal
+// phase: 6; a swap or sign flip: 0), on the 2^-c of the register that
+// satisfies its c controls.
+double op_flops(const Op &op, int M)
+{
+    double per = 0.0;
+    const double *u = op.u;
+    if (op.type == kOpMat)
+        per = (u[1] != 0.0 || u[7] != 0.0) && (u[0] != 0.0 || u[6] != 0.0) ? 10.0 : 6.0;
+    else if (op.type == kOpDiag)
+        per = 6.0;
+    return per * std::ldexp(1.0, M - __builtin_popcountll(op.cmask));
 }
 
 // ------------------------------------------------------------- scheduling
@@ -636,7 +656,7 @@ void build_tile_args(const qsim_state *s, const std::vector<Op> &ops, const Pass
                 t.kind = kTPair;
                 t.c[0] = (R)u[0]; t.c[1] = (R)u[2]; t.c[2] = (R)u[4]; t.c[3] = (R)u[6];
                 t.c[4] = (R)u[1]; t.c[5] = (R)u[7];
-                t.has_w = (u[1] != 0.0 || u[7] != 0.0) ? 1 : 0;
+                t.form = (u[1] != 0.0 || u[7] != 0.0) ? (u[0] == 0.0 && u[6] == 0.0 ? 2 : 1) : 0;
                 break;
             case kOpSwap:
                 t.kind = kTSwap;
@@ -763,7 +783,10 @@ int run_ops(qsim_state *s, const std::vector<Op> &stream)
             A.psi = psi;
             A.scale_in = scale_pending ? norm_sum + 1 : nullptr;
             A.norm_out = p.norm_after ? s->d_tile_norm : nullptr;
-            Timed t(s, 1, full);
+            double flops = 0.0;
+            for (size_t i = p.first; i < p.first + p.count; ++i)
+                flops += op_flops(ops[i], s->M);
+            Timed t(s, 1, full, flops);
             HIP_TRY(launch_tile<R>(A, G, s->stream), "fused pass launch");
             t.done();
             scale_pending = false;
@@ -1380,6 +1403,8 @@ int qsim_plan(int num_qubits, int dtype, const qsim_options *opt, const qsim_gat
         info.first_op = (uint32_t)plan[i].first;
         info.n_ops = (uint32_t)plan[i].count;
         info.norm_after = plan[i].norm_after ? 1u : 0u;
+        for (size_t j = plan[i].first; j < plan[i].first + plan[i].count; ++j)
+            info.flops += op_flops(ops[j], num_qubits);
         if (plan[i].fused) {
             char why[160];
             int G = 0;

@@ -47,69 +47,121 @@ __device__ __forceinline__ void st2(cplx<double> *p, cplx<double> a, cplx<double
     reinterpret_cast<double2 *>(p)[1] = make_double2(b.re, b.im);
 }
 
-// One operation on the registers of group bit P.  Controls on group bits
-// (mask rc over the register index) select registers with a uniform test per
-// register; the target bit is a compile-time property of r.
-template <typename R, int G, int P>
-__device__ __forceinline__ void apply_at(const TileOp<R> &op, cplx<R> (&x)[1 << G])
+// Register-pair loops of one operation on group bit P, specialised at
+// compile time.  Register r of a quantum holds the amplitude whose group bits
+// spell r, so the target bit is a compile-time property of r.  C: controls
+// on group bits (mask rc over the register index) are tested, with a uniform
+// test per register; without them every register takes part.  F: the form
+// of a kTPair, 0 = real 2x2 m, 1 = m plus i*w on the diagonal, 2 = the same
+// with m00 = m11 = 0 (a perturbed X).
+template <typename R, int G, int P, int F, bool C>
+__device__ __forceinline__ void pair_loop(const TileOp<R> &op, cplx<R> (&x)[1 << G])
 {
-    const uint32_t rc = op.rc;
-    switch (op.kind) {
-    case kTPair: {
-        // out0 = m00 a + m01 b + i w0 a,  out1 = m10 a + m11 b + i w1 b
-        const R m00 = op.c[0], m01 = op.c[1], m10 = op.c[2], m11 = op.c[3];
-        const R w0 = op.c[4], w1 = op.c[5];
-        const bool has_w = op.has_w;
+    // out0 = m00 a + m01 b + i w0 a,  out1 = m10 a + m11 b + i w1 b
+    const R m00 = op.c[0], m01 = op.c[1], m10 = op.c[2], m11 = op.c[3];
+    const R w0 = op.c[4], w1 = op.c[5];
+    const uint32_t rc = C ? op.rc : 0u;
 #pragma unroll
-        for (int r = 0; r < (1 << G); ++r) {
-            if ((r & (1 << P)) || ((uint32_t)r & rc) != rc)
-                continue;
-            const int r1 = r | (1 << P);
-            const cplx<R> a = x[r], b = x[r1];
-            cplx<R> na = {m00 * a.re + m01 * b.re, m00 * a.im + m01 * b.im};
-            cplx<R> nb = {m10 * a.re + m11 * b.re, m10 * a.im + m11 * b.im};
-            if (has_w) {
+    for (int r = 0; r < (1 << G); ++r) {
+        if ((r & (1 << P)) || (C && ((uint32_t)r & rc) != rc))
+            continue;
+        const int r1 = r | (1 << P);
+        const cplx<R> a = x[r], b = x[r1];
+        cplx<R> na, nb;
+        if (F == 2) {
+            na = {m01 * b.re - w0 * a.im, m01 * b.im + w0 * a.re};
+            nb = {m10 * a.re - w1 * b.im, m10 * a.im + w1 * b.re};
+        } else {
+            na = {m00 * a.re + m01 * b.re, m00 * a.im + m01 * b.im};
+            nb = {m10 * a.re + m11 * b.re, m10 * a.im + m11 * b.im};
+            if (F == 1) {
                 na.re -= w0 * a.im;
                 na.im += w0 * a.re;
                 nb.re -= w1 * b.im;
                 nb.im += w1 * b.re;
             }
-            x[r] = na;
-            x[r1] = nb;
         }
-        break;
+        x[r] = na;
+        x[r1] = nb;
     }
-    case kTSwap: {
+}
+
+template <typename R, int G, int P, bool C>
+__device__ __forceinline__ void swap_loop(const TileOp<R> &op, cplx<R> (&x)[1 << G])
+{
+    const uint32_t rc = C ? op.rc : 0u;
 #pragma unroll
-        for (int r = 0; r < (1 << G); ++r) {
-            if ((r & (1 << P)) || ((uint32_t)r & rc) != rc)
-                continue;
-            const int r1 = r | (1 << P);
-            const cplx<R> a = x[r];
-            x[r] = x[r1];
-            x[r1] = a;
-        }
-        break;
+    for (int r = 0; r < (1 << G); ++r) {
+        if ((r & (1 << P)) || (C && ((uint32_t)r & rc) != rc))
+            continue;
+        const int r1 = r | (1 << P);
+        const cplx<R> a = x[r];
+        x[r] = x[r1];
+        x[r1] = a;
     }
-    case kTDiagIn: {
-        const cplx<R> d0 = {op.c[0], op.c[1]}, d1 = {op.c[2], op.c[3]};
+}
+
+template <typename R, int G, int P, bool C>
+__device__ __forceinline__ void diag_loop(const TileOp<R> &op, cplx<R> (&x)[1 << G])
+{
+    const cplx<R> d0 = {op.c[0], op.c[1]}, d1 = {op.c[2], op.c[3]};
+    const uint32_t rc = C ? op.rc : 0u;
 #pragma unroll
-        for (int r = 0; r < (1 << G); ++r) {
-            if (((uint32_t)r & rc) != rc)
-                continue;
-            x[r] = cmul(x[r], ((r >> P) & 1) ? d1 : d0);
-        }
-        break;
+    for (int r = 0; r < (1 << G); ++r) {
+        if (C && ((uint32_t)r & rc) != rc)
+            continue;
+        x[r] = cmul(x[r], ((r >> P) & 1) ? d1 : d0);
     }
-    default: {  // kTNegIn
+}
+
+template <typename R, int G, int P, bool C>
+__device__ __forceinline__ void neg_loop(const TileOp<R> &op, cplx<R> (&x)[1 << G])
+{
+    const uint32_t rc = C ? op.rc : 0u;
 #pragma unroll
-        for (int r = 0; r < (1 << G); ++r) {
-            if (!((r >> P) & 1) || ((uint32_t)r & rc) != rc)
-                continue;
-            x[r] = {-x[r].re, -x[r].im};
-        }
-        break;
+    for (int r = 0; r < (1 << G); ++r) {
+        if (!((r >> P) & 1) || (C && ((uint32_t)r & rc) != rc))
+            continue;
+        x[r] = {-x[r].re, -x[r].im};
     }
+}
+
+// One operation on the registers of group bit P.  Operations without a
+// control on a group bit (the common case) take loops with no per-register
+// tests.
+template <typename R, int G, int P>
+__device__ __forceinline__ void apply_at(const TileOp<R> &op, cplx<R> (&x)[1 << G])
+{
+    const bool ctl = op.rc != 0;
+    switch (op.kind) {
+    case kTPair:
+        if (ctl)
+            pair_loop<R, G, P, 1, true>(op, x);
+        else if (op.form == 0)
+            pair_loop<R, G, P, 0, false>(op, x);
+        else if (op.form == 1)
+            pair_loop<R, G, P, 1, false>(op, x);
+        else
+            pair_loop<R, G, P, 2, false>(op, x);
+        break;
+    case kTSwap:
+        if (ctl)
+            swap_loop<R, G, P, true>(op, x);
+        else
+            swap_loop<R, G, P, false>(op, x);
+        break;
+    case kTDiagIn:
+        if (ctl)
+            diag_loop<R, G, P, true>(op, x);
+        else
+            diag_loop<R, G, P, false>(op, x);
+        break;
+    default:  // kTNegIn
+        if (ctl)
+            neg_loop<R, G, P, true>(op, x);
+        else
+            neg_loop<R, G, P, false>(op, x);
+        break;
     }
 }
 
@@ -263,8 +315,16 @@ __device__ __forceinline__ void group_layout(const TileArgs<R> &A, uint32_t gi, 
 // registers (T * 2^G = 2^k).  While a tile is being worked on, the first
 // group's quanta of the workgroup's next tile are already being loaded, so
 // HBM traffic overlaps the register and LDS work.
+// Waves per SIMD the register budget is sized for.  complex64 with G = 4 is
+// the bench shape: two 512-thread workgroups per CU (LDS allows two 64 KiB
+// tiles) need four waves per SIMD, i.e. at most 128 VGPRs; the compiler
+// otherwise settles just above that and halves the resident workgroups.
+template <typename R, int G>
+constexpr int kTileWaves = (sizeof(R) == 4 && G == 4) ? 4 : 1;
+
 template <typename R, int G, int T>
-__global__ void __launch_bounds__(T) k_tile(const TileArgs<R> A)
+__global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kTileWaves<R, G>)))
+k_tile(const TileArgs<R> A)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ double wsum[T / 64];

@@ -53,12 +53,26 @@ def test_binding_loads_and_reports_errors_as_text(libpath):
     assert isinstance(L.qsim_last_error(), bytes)
 
 
-def test_struct_layouts():
+def test_struct_layouts(tmp_path):
     assert cg.GATE_DTYPE.itemsize == 24
-    assert ctypes.sizeof(q.qsim_error_model) == 40
-    assert ctypes.sizeof(q.qsim_stats) == 80
     text = open(HEADER).read()
     assert "double theta;" in text and "uint32_t kind;" in text
+    # every struct the binding mirrors has the size the C compiler gives it
+    names = ["qsim_gate", "qsim_error_model", "qsim_options", "qsim_stats", "qsim_pass_info",
+             "qsim_request", "qsim_result", "qsim_serve_options"]
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include "qsim.h"\nint main(void) {\n' +
+                   "".join(f'printf("%zu\\n", sizeof({n}));\n' for n in names) +
+                   "return 0; }\n")
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    sizes = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                            check=True).stdout.split()]
+    mirror = {"qsim_gate": cg.GATE_DTYPE.itemsize}
+    for n in names[1:]:
+        mirror[n] = ctypes.sizeof(getattr(q, n))
+    assert sizes == [mirror[n] for n in names]
 
 
 def test_argument_errors_without_gpu(libpath):

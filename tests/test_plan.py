@@ -113,3 +113,20 @@ def test_toffoli_run_whose_controls_cover_the_tile():
         opt = q.make_options(tile_bits=10, group_bits=group)
         passes, nops = q.qsim_plan(10, q.QSIM_C128, gates, opt)
         assert [p["fused"] for p in passes] == [1] and passes[0]["n_ops"] == nops == 12
+
+
+@pytest.mark.parametrize("gate,sigma,per_amp,controls", [
+    ((cg.H, 3), None, 6, 0),                 # real 2x2
+    ((cg.H, 3), 0.1, 10, 0),                 # real 2x2 plus i*w on the diagonal
+    ((cg.X, 3), None, 0, 0),                 # exact swap
+    ((cg.X, 3), 0.1, 6, 0),                  # perturbed X: zero diagonal plus i*w
+    ((cg.CNOT, 3, 7), 0.1, 6, 1),
+    ((cg.TOFFOLI, 3, 7, 8), 0.1, 6, 2),
+    ((cg.RZ, 5, -1, -1, 0.4), None, 6, 0),   # diagonal phase
+    ((cg.Z, 5), None, 0, 0),                 # exact sign flip
+])
+def test_pass_flops_count_each_operations_2x2(gate, sigma, per_amp, controls):
+    M = 10
+    passes, nops = q.qsim_plan(M, q.QSIM_C64, cg.gates_from_list([gate]), sigma=sigma, seed=3)
+    assert nops == 1 and len(passes) == 1
+    assert passes[0]["flops"] == per_amp * 2.0 ** (M - controls)
