@@ -610,12 +610,38 @@ void build_tile_args(const qsim_state *s, const std::vector<Op> &ops, const Pass
     }
     close_group(A.nops);
     A.ngroups = (uint32_t)groups.size();
+    double phase_re = 1.0, phase_im = 0.0;  // global phase of the pass's diagonals
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         std::vector<uint32_t> bits = groups[gi].second;
-        // pad with the highest free tile bits (keeps tile bit 0 outside the
-        // group, so neighbouring threads touch neighbouring LDS words)
+        auto absent = [&](uint32_t b) {
+            return std::find(bits.begin(), bits.end(), b) == bits.end();
+        };
+        // pad first with the tile bits that the group's uncontrolled
+        // diagonal operations act on, most used first (on a group bit such
+        // an operation scales half of the registers; on any other bit it
+        // costs a factor on all of them), then with the highest free tile
+        // bits (keeps tile bit 0 outside the group, so neighbouring threads
+        // touch neighbouring LDS words)
+        {
+            const uint32_t gf = group_first(groups[gi].first), gc = group_count(groups[gi].first);
+            int uses[64] = {0};
+            for (uint32_t o = gf; o < gf + gc; ++o) {
+                const Op &op = ops[p.first + o];
+                if (!needs_tile_target(op) && tpos_of[op.target] >= 0)
+                    ++uses[tpos_of[op.target]];
+            }
+            while ((int)bits.size() < G) {
+                int best = -1;
+                for (int b = 0; b < k; ++b)
+                    if (uses[b] > 0 && absent((uint32_t)b) && (best < 0 || uses[b] > uses[best]))
+                        best = b;
+                if (best < 0)
+                    break;
+                bits.push_back((uint32_t)best);
+            }
+        }
         for (int b = k - 1; b >= 0 && (int)bits.size() < G; --b)
-            if (std::find(bits.begin(), bits.end(), (uint32_t)b) == bits.end())
+            if (absent((uint32_t)b))
                 bits.push_back((uint32_t)b);
         std::sort(bits.begin(), bits.end());
         uint32_t w = groups[gi].first;
@@ -662,8 +688,22 @@ void build_tile_args(const qsim_state *s, const std::vector<Op> &ops, const Pass
                 t.kind = kTSwap;
                 break;
             case kOpDiag:
-                t.kind = gp >= 0 ? kTDiagIn : kTDiagOut;
-                t.c[0] = (R)u[0]; t.c[1] = (R)u[1]; t.c[2] = (R)u[6]; t.c[3] = (R)u[7];
+                if (op.cmask == 0) {
+                    // diag(d0, d1) = d0 diag(1, d1/d0): d0 multiplies the
+                    // whole register and joins the pass's global phase
+                    const double d0r = u[0], d0i = u[1], d1r = u[6], d1i = u[7];
+                    const double n0 = d0r * d0r + d0i * d0i;
+                    const double qr = (d1r * d0r + d1i * d0i) / n0;
+                    const double qi = (d1i * d0r - d1r * d0i) / n0;
+                    const double pr = phase_re * d0r - phase_im * d0i;
+                    phase_im = phase_re * d0i + phase_im * d0r;
+                    phase_re = pr;
+                    t.kind = gp >= 0 ? kTPhaseIn : kTDiagOut;
+                    t.c[0] = R(1); t.c[1] = R(0); t.c[2] = (R)qr; t.c[3] = (R)qi;
+                } else {
+                    t.kind = kTDiagIn;
+                    t.c[0] = (R)u[0]; t.c[1] = (R)u[1]; t.c[2] = (R)u[6]; t.c[3] = (R)u[7];
+                }
                 break;
             default:
                 t.kind = gp >= 0 ? kTNegIn : kTNegOut;
@@ -671,6 +711,9 @@ void build_tile_args(const qsim_state *s, const std::vector<Op> &ops, const Pass
             }
         }
     }
+    A.phase[0] = (R)phase_re;
+    A.phase[1] = (R)phase_im;
+    A.use_phase = (phase_re != 1.0 || phase_im != 0.0) ? 1u : 0u;
 }
 
 // Internal consistency of a fused pass's arguments (used by qsim_plan).
@@ -732,6 +775,10 @@ bool tile_args_consistent(const TileArgs<R> &A, int G, const std::vector<Op> &op
             const Op &op = ops[p.first + o];
             const TileOp<R> &t = A.ops[o];
             const bool in_tile = (A.smask >> op.target) & 1u;
+            if ((t.kind == kTPhaseIn || t.kind >= kTDiagOut) && op.cmask != 0) {
+                snprintf(why, n, "op %u: controlled diagonal taken as a phase", o);
+                return false;
+            }
             if (t.kind <= kTNegIn) {
                 if (!in_tile || t.gpos >= (uint32_t)G || group_bit(w, t.gpos) != t.tpos) {
                     snprintf(why, n, "op %u target not on its group bit", o);

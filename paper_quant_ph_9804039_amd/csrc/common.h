@@ -133,10 +133,11 @@ constexpr int kMaxRuns = 16;  // runs of consecutive qubits in a tile set or its
 // amplitudes spanned by the group bits; see the tile kernel).
 enum TileOpKind : uint8_t {
     kTPair = 0,     // real 2x2 m plus i*w on the diagonal (H, perturbed H / X)
+    kTPhaseIn = 1,  // uncontrolled diag(1, q) on a group bit (the diagonal's d0 is global)
     kTSwap = 2,     // exact exchange
-    kTDiagIn = 3,   // diag(d0, d1) on a group bit
+    kTDiagIn = 3,   // controlled diag(d0, d1) on a group bit
     kTNegIn = 4,    // exact sign flip on a group bit
-    kTDiagOut = 5,  // uncontrolled diag on a bit outside the group: one factor per quantum
+    kTDiagOut = 5,  // uncontrolled diag(1, q) on a bit outside the group: one factor per quantum
     kTNegOut = 6,   // uncontrolled sign flip on a bit outside the group
 };
 
@@ -183,6 +184,8 @@ struct TileArgs {
     uint32_t srun[kMaxRuns];           //   start | length << 8: tile index bits ->
     uint32_t crun[kMaxRuns];           //   tile qubits; tile number bits -> the rest
     uint32_t group[kMaxGroups];        // see group_first / group_count / group_bit
+    R phase[2];                        // global phase of the pass's uncontrolled diagonals
+    uint32_t use_phase;                // phase != 1
     TileOp<R> ops[kMaxPassOps];
 };
 

@@ -114,6 +114,17 @@ __device__ __forceinline__ void diag_loop(const TileOp<R> &op, cplx<R> (&x)[1 <<
     }
 }
 
+// diag(1, q) on group bit P: only the registers whose bit P is set move.
+template <typename R, int G, int P>
+__device__ __forceinline__ void phase_loop(const TileOp<R> &op, cplx<R> (&x)[1 << G])
+{
+    const cplx<R> q = {op.c[2], op.c[3]};
+#pragma unroll
+    for (int r = 0; r < (1 << G); ++r)
+        if ((r >> P) & 1)
+            x[r] = cmul(x[r], q);
+}
+
 template <typename R, int G, int P, bool C>
 __device__ __forceinline__ void neg_loop(const TileOp<R> &op, cplx<R> (&x)[1 << G])
 {
@@ -150,6 +161,9 @@ __device__ __forceinline__ void apply_at(const TileOp<R> &op, cplx<R> (&x)[1 << 
         else
             swap_loop<R, G, P, false>(op, x);
         break;
+    case kTPhaseIn:  // never controlled
+        phase_loop<R, G, P>(op, x);
+        break;
     case kTDiagIn:
         if (ctl)
             diag_loop<R, G, P, true>(op, x);
@@ -166,17 +180,23 @@ __device__ __forceinline__ void apply_at(const TileOp<R> &op, cplx<R> (&x)[1 << 
 }
 
 // Apply the operations [first, first + cnt) of a group to one quantum.
-// Uncontrolled diagonal operations on bits outside the group commute with
-// everything else in the group (those act on group bits only), and their
-// factor is the same for all registers of the quantum: they are multiplied
-// into one factor F, applied once at the end.
+// An uncontrolled diagonal reaches the kernel as diag(1, q), its d0 having
+// been moved into the pass's global phase (a scalar commutes with
+// everything).  On a bit outside the group it commutes with everything else
+// in the group (those act on group bits only), and its factor is the same
+// for all registers of the quantum: such factors are multiplied into one
+// factor F, applied once at the end; the last group's F starts from the
+// global phase.
 template <typename R, int G>
 __device__ __forceinline__ void apply_group(const TileArgs<R> &A, uint32_t first, uint32_t cnt,
-                                            cplx<R> (&x)[1 << G], uint32_t j0, uint64_t base)
+                                            cplx<R> (&x)[1 << G], uint32_t j0, uint64_t base,
+                                            bool last)
 {
     static_assert(G >= 3 && G <= 5, "group bits");
-    cplx<R> F = {R(1), R(0)};
-    bool useF = false;
+    // the last group also carries the pass's global phase
+    const bool ph = last && A.use_phase != 0;
+    cplx<R> F = ph ? cplx<R>{A.phase[0], A.phase[1]} : cplx<R>{R(1), R(0)};
+    bool useF = ph;
     for (uint32_t o = first; o < first + cnt; ++o) {
         const TileOp<R> op = A.ops[o];  // whole descriptor at once: one scalar wait
         if ((base & op.cm_out) != op.cm_out || (j0 & op.qc) != op.qc)
@@ -374,7 +394,8 @@ k_tile(const TileArgs<R> A)
 #pragma unroll
         for (int i = 0; i < G; ++i)
             e[i] = e0[i];
-        apply_group<R, G>(A, group_first(A.group[0]), group_count(A.group[0]), x, j0, base);
+        apply_group<R, G>(A, group_first(A.group[0]), group_count(A.group[0]), x, j0, base,
+                          A.ngroups == 1);
         for (uint32_t gi = 1; gi < A.ngroups; ++gi) {
             // registers -> LDS in the old layout, LDS -> registers in the new one
             if (pair0) {
@@ -398,7 +419,8 @@ k_tile(const TileArgs<R> A)
                     x[r] = tile[elem_index<G>(j0, e, r)];
             }
             __syncthreads();
-            apply_group<R, G>(A, group_first(A.group[gi]), group_count(A.group[gi]), x, j0, base);
+            apply_group<R, G>(A, group_first(A.group[gi]), group_count(A.group[gi]), x, j0, base,
+                              gi + 1 == A.ngroups);
         }
         // registers -> HBM in the last group's layout
         uint64_t o[G];
