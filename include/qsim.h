@@ -195,7 +195,12 @@ int qsim_set_amplitudes(qsim_state *s, uint64_t offset, uint64_t count, const do
  * run in one persistent launch, one register per workgroup, which needs the
  * register to fit the workgroup's LDS (num_qubits <= 14 for QSIM_C64,
  * <= 13 for QSIM_C128); EINVAL beyond that.  Synchronous.  Runs on `device`
- * 0 unless QSIM_DEVICE is set in the environment. */
+ * 0 unless QSIM_DEVICE is set in the environment.  The kernel variant (one
+ * LDS sweep per gate, or the register held in registers with 4 or 5 group
+ * qubits) is picked by timing each on one round of trials, once per
+ * (register size, dtype, gate count, error kinds) and process, optionally
+ * cached in the file QSIM_TUNE_CACHE names; QSIM_TRIAL_VARIANT = 0..3 forces
+ * one where it can run. */
 int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits, int dtype,
                     const qsim_error_model *base, uint64_t n_trials, double *out_F);
 

@@ -15,6 +15,8 @@
 // phase flip Z_q of psi is Z_q of s times -1 when q is in X.  The fidelity
 // reads s at i xor X.  All of this is exact, so the result equals the
 // flip-by-flip evolution.
+#include <algorithm>
+
 #include "launch.h"
 
 namespace qsim {
@@ -32,7 +34,10 @@ struct TrialOp {
     uint32_t cval;       // values the controls must have in the stored register
     uint32_t neg_val;    // kOpNeg: the target value whose amplitudes change sign
     uint32_t zmask;      // phase flips after the gate, on stored-register qubits
-    uint32_t pad[2];
+    uint32_t form;       // kOpMat: 0 real 2x2; 1 real off-diagonal, complex
+                         // diagonal; 2 the same with a zero real diagonal;
+                         // 3 anything else
+    uint32_t pad;
 };
 
 // Matrix of one gate with angle error eps, as the host lowering builds it:
@@ -83,6 +88,107 @@ __device__ void gate_matrix(uint32_t kind, double theta, double eps, uint32_t &t
     }
 }
 
+// A trial gate as the register-group variants read it from global memory
+// (built by the preparation kernel for the group the gate sits in):
+//   meta  = type | form << 4 | neg_val << 8 | P << 12 | target << 16, P =
+//           the target's position among the group qubits, 15 when it is not
+//           one;
+//   regs  = rm | rv << 8 | rz << 16: controls on group qubits and the values
+//           they need, and phase flips on group qubits, over the register
+//           index;
+//   lm, lv: controls on the other qubits and their values, over the thread's
+//           base index; zmask: all phase flips after the gate.
+// A diagonal is kept as diag(1, q) with u[3] = q (the trial's global phase
+// does not change its fidelity).
+template <typename R>
+struct TrialGateOp {
+    cplx<R> u[4];
+    uint32_t meta;
+    uint32_t regs;
+    uint32_t lm;
+    uint32_t lv;
+    uint32_t zmask;
+    uint32_t pad[3];
+};
+
+// Build the trial's operations for gates [c0, c0 + cn) of the circuit in
+// LDS (ops), drawing the chunk's flips (one Philox block per (step, qubit))
+// and tracking the X mask of bit flips across the chunk; xmask_at[g] is the
+// mask before gate g of the chunk, xmask_at[cn] the mask after it.  Every
+// thread of the workgroup calls it; it begins and ends with a barrier.
+template <typename R, int T>
+__device__ void build_chunk(const TrialGate *gates, uint32_t c0, uint32_t cn, uint32_t M,
+                            double sigma, uint64_t thr_b, uint64_t thr_p, bool draws_flip,
+                            uint64_t seed, uint64_t trial, uint32_t X, TrialOp<R> *ops,
+                            uint32_t *bmask, uint32_t *zmask, uint32_t *xmask_at)
+{
+    const uint32_t tid = threadIdx.x;
+    __syncthreads();
+    for (uint32_t i = tid; i < cn; i += T) {
+        bmask[i] = 0;
+        zmask[i] = 0;
+    }
+    __syncthreads();
+    if (draws_flip) {
+        for (uint32_t i = tid; i < cn * M; i += T) {
+            const uint32_t g = i / M, q = i % M;
+            const u64x4 r = philox4x64_10(c0 + g, q, kStreamFlip, 0, seed, trial);
+            if ((r.w[0] >> 32) < thr_b)
+                atomicOr(&bmask[g], 1u << q);
+            if ((r.w[1] >> 32) < thr_p)
+                atomicOr(&zmask[g], 1u << q);
+        }
+    }
+    __syncthreads();
+    // X mask before each gate of the chunk (a serial scan)
+    if (tid == 0) {
+        uint32_t x = X;
+        for (uint32_t g = 0; g < cn; ++g) {
+            xmask_at[g] = x;
+            x ^= bmask[g];
+        }
+        xmask_at[cn] = x;
+    }
+    __syncthreads();
+    for (uint32_t g = tid; g < cn; g += T) {
+        const TrialGate gd = gates[c0 + g];
+        const double eps = sigma > 0.0 ? sigma * step_gaussian(seed, trial, c0 + g) : 0.0;
+        uint32_t type;
+        double u[8];
+        gate_matrix(gd.kind, gd.theta, eps, type, u);
+        const uint32_t xg = xmask_at[g];
+        const bool flipped = (xg >> gd.target) & 1u;
+        TrialOp<R> op;
+        if (flipped) {
+            // X U X: swap rows and columns
+            op.u[0] = {(R)u[6], (R)u[7]};
+            op.u[1] = {(R)u[4], (R)u[5]};
+            op.u[2] = {(R)u[2], (R)u[3]};
+            op.u[3] = {(R)u[0], (R)u[1]};
+        } else {
+            op.u[0] = {(R)u[0], (R)u[1]};
+            op.u[1] = {(R)u[2], (R)u[3]};
+            op.u[2] = {(R)u[4], (R)u[5]};
+            op.u[3] = {(R)u[6], (R)u[7]};
+        }
+        op.type = type;
+        op.target = gd.target;
+        op.cmask = gd.cmask;
+        op.cval = gd.cmask & ~xg;
+        op.neg_val = flipped ? 0u : 1u;
+        // phase flips follow this step's bit flips; Z_q on the true register
+        // is Z_q on the stored one up to a global sign
+        op.zmask = zmask[g];
+        const bool real_off = u[3] == 0.0 && u[5] == 0.0;
+        const bool real_diag = u[1] == 0.0 && u[7] == 0.0;
+        const bool zero_diag = u[0] == 0.0 && u[6] == 0.0;
+        op.form = !real_off ? 3u : real_diag ? 0u : zero_diag ? 2u : 1u;
+        op.pad = 0;
+        ops[g] = op;
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -106,7 +212,6 @@ __global__ void __launch_bounds__(T) k_trials(const TrialGate *gates, uint32_t n
     __shared__ uint32_t bmask[kChunk], zmask[kChunk], xmask_at[kChunk + 1];
     __shared__ double red[4][T / 64];
     const uint32_t tid = threadIdx.x;
-    const bool draws_angle = sigma > 0.0;
     const bool draws_flip = p_bit > 0.0 || p_phase > 0.0;
     const uint64_t thr_b = flip_threshold(p_bit), thr_p = flip_threshold(p_phase);
 
@@ -117,67 +222,8 @@ __global__ void __launch_bounds__(T) k_trials(const TrialGate *gates, uint32_t n
         uint32_t X = 0;  // bit flips so far (uniform)
         for (uint32_t c0 = 0; c0 < n; c0 += kChunk) {
             const uint32_t cn = min((uint32_t)kChunk, n - c0);
-            __syncthreads();
-            for (uint32_t i = tid; i < cn; i += T) {
-                bmask[i] = 0;
-                zmask[i] = 0;
-            }
-            __syncthreads();
-            // flip draws of the chunk: one Philox block per (step, qubit)
-            if (draws_flip) {
-                for (uint32_t i = tid; i < cn * M; i += T) {
-                    const uint32_t g = i / M, q = i % M;
-                    const u64x4 r = philox4x64_10(c0 + g, q, kStreamFlip, 0, seed, trial);
-                    if ((r.w[0] >> 32) < thr_b)
-                        atomicOr(&bmask[g], 1u << q);
-                    if ((r.w[1] >> 32) < thr_p)
-                        atomicOr(&zmask[g], 1u << q);
-                }
-            }
-            __syncthreads();
-            // X mask before each gate of the chunk (a serial scan)
-            if (tid == 0) {
-                uint32_t x = X;
-                for (uint32_t g = 0; g < cn; ++g) {
-                    xmask_at[g] = x;
-                    x ^= bmask[g];
-                }
-                xmask_at[cn] = x;
-            }
-            __syncthreads();
-            // the chunk's gates as applied to the stored register
-            for (uint32_t g = tid; g < cn; g += T) {
-                const TrialGate gd = gates[c0 + g];
-                const double eps = draws_angle ? sigma * step_gaussian(seed, trial, c0 + g) : 0.0;
-                uint32_t type;
-                double u[8];
-                gate_matrix(gd.kind, gd.theta, eps, type, u);
-                const uint32_t xg = xmask_at[g];
-                const bool flipped = (xg >> gd.target) & 1u;
-                TrialOp<R> op;
-                if (flipped) {
-                    // X U X: swap rows and columns
-                    op.u[0] = {(R)u[6], (R)u[7]};
-                    op.u[1] = {(R)u[4], (R)u[5]};
-                    op.u[2] = {(R)u[2], (R)u[3]};
-                    op.u[3] = {(R)u[0], (R)u[1]};
-                } else {
-                    op.u[0] = {(R)u[0], (R)u[1]};
-                    op.u[1] = {(R)u[2], (R)u[3]};
-                    op.u[2] = {(R)u[4], (R)u[5]};
-                    op.u[3] = {(R)u[6], (R)u[7]};
-                }
-                op.type = type;
-                op.target = gd.target;
-                op.cmask = gd.cmask;
-                op.cval = gd.cmask & ~xg;
-                op.neg_val = flipped ? 0u : 1u;
-                // phase flips follow this step's bit flips; Z_q on the true
-                // register is Z_q on the stored one up to a global sign
-                op.zmask = zmask[g];
-                ops[g] = op;
-            }
-            __syncthreads();
+            build_chunk<R, T>(gates, c0, cn, M, sigma, thr_b, thr_p, draws_flip, seed, trial, X,
+                              ops, bmask, zmask, xmask_at);
             for (uint32_t g = 0; g < cn; ++g) {
                 const TrialOp<R> op = ops[g];
                 const uint32_t tb = 1u << op.target;
@@ -246,6 +292,395 @@ __global__ void __launch_bounds__(T) k_trials(const TrialGate *gates, uint32_t n
     }
 }
 
+// --------------------------------------------------------------------------
+// Variants 2 and 3: the register in registers.  Each of the T = 2^(M-G)
+// threads holds 2^G amplitudes of the trial's register: register r holds
+// the stored amplitude whose index is the thread's base index j0 (its own
+// bits on the other qubits) plus the group qubits spelling r.  The host
+// splits the circuit into groups of consecutive gates whose non-diagonal
+// targets fall on at most G qubits; inside a group every gate is a fixed
+// pattern of register pairs (a diagonal on another qubit is a per-thread
+// factor), and between groups with different qubits the register is
+// re-partitioned through LDS.  Gates are built per chunk of whole groups.
+
+
+// Qubit i of a group word (G <= 5 qubits < 16, four bits each, ascending).
+__device__ __forceinline__ uint32_t gq(uint32_t w, int i) { return (w >> (4 * i)) & 15u; }
+
+template <int G>
+__device__ __forceinline__ void trial_layout(uint32_t w, uint32_t &j0, uint32_t &gmask)
+{
+    j0 = threadIdx.x;
+    gmask = 0;
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        const uint32_t b = gq(w, i);
+        gmask |= 1u << b;
+        j0 = ((j0 >> b) << (b + 1)) | (j0 & ((1u << b) - 1u));
+    }
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t trial_index(uint32_t j0, uint32_t w, int r)
+{
+    uint32_t j = j0;
+#pragma unroll
+    for (int i = 0; i < G; ++i)
+        if (r & (1 << i))
+            j |= 1u << gq(w, i);
+    return j;
+}
+
+// A 2x2 on group position P.  F: matrix form (see TrialOp).  C: controls on
+// group qubits (mask rm over the register index, required values rv): an
+// inactive pair takes the identity instead, chosen per pair by a uniform
+// select of the coefficients (form 1 holds the identity), so the register
+// pattern stays fixed.
+template <typename R, int G, int P, int F, bool C>
+__device__ __forceinline__ void trial_pair(const cplx<R> (&u)[4], uint32_t rm, uint32_t rv,
+                                           cplx<R> (&x)[1 << G])
+{
+#pragma unroll
+    for (int r = 0; r < (1 << G); ++r) {
+        if (r & (1 << P))
+            continue;
+        const int r1 = r | (1 << P);
+        const cplx<R> a = x[r], b = x[r1];
+        if (C) {
+            const bool on = ((uint32_t)r & rm) == rv;
+            const R m00 = on ? u[0].re : R(1), m01 = on ? u[1].re : R(0);
+            const R m10 = on ? u[2].re : R(0), m11 = on ? u[3].re : R(1);
+            const R w0 = on ? u[0].im : R(0), w1 = on ? u[3].im : R(0);
+            x[r] = {m00 * a.re + m01 * b.re - w0 * a.im, m00 * a.im + m01 * b.im + w0 * a.re};
+            x[r1] = {m10 * a.re + m11 * b.re - w1 * b.im, m10 * a.im + m11 * b.im + w1 * b.re};
+        } else if (F == 0) {
+            x[r] = {u[0].re * a.re + u[1].re * b.re, u[0].re * a.im + u[1].re * b.im};
+            x[r1] = {u[2].re * a.re + u[3].re * b.re, u[2].re * a.im + u[3].re * b.im};
+        } else if (F == 1) {
+            x[r] = {u[0].re * a.re + u[1].re * b.re - u[0].im * a.im,
+                    u[0].re * a.im + u[1].re * b.im + u[0].im * a.re};
+            x[r1] = {u[2].re * a.re + u[3].re * b.re - u[3].im * b.im,
+                     u[2].re * a.im + u[3].re * b.im + u[3].im * b.re};
+        } else if (F == 2) {
+            x[r] = {u[1].re * b.re - u[0].im * a.im, u[1].re * b.im + u[0].im * a.re};
+            x[r1] = {u[2].re * a.re - u[3].im * b.im, u[2].re * a.im + u[3].im * b.re};
+        } else {
+            x[r] = cmad2(u[0], a, u[1], b);
+            x[r1] = cmad2(u[2], a, u[3], b);
+        }
+    }
+}
+
+template <typename R, int G, int P, bool C>
+__device__ __forceinline__ void trial_swap(uint32_t rm, uint32_t rv, cplx<R> (&x)[1 << G])
+{
+#pragma unroll
+    for (int r = 0; r < (1 << G); ++r) {
+        if ((r & (1 << P)) || (C && ((uint32_t)r & rm) != rv))
+            continue;
+        const int r1 = r | (1 << P);
+        const cplx<R> a = x[r];
+        x[r] = x[r1];
+        x[r1] = a;
+    }
+}
+
+// diag(1, q) or a sign flip on group position P (registers whose bit P is
+// `on`), under controls on group qubits.
+template <typename R, int G, int P>
+__device__ __forceinline__ void trial_phase(bool neg, uint32_t on, cplx<R> q, uint32_t rm,
+                                            uint32_t rv, cplx<R> (&x)[1 << G])
+{
+#pragma unroll
+    for (int r = 0; r < (1 << G); ++r) {
+        if ((((uint32_t)r >> P) & 1u) != on || ((uint32_t)r & rm) != rv)
+            continue;
+        x[r] = neg ? cplx<R>{-x[r].re, -x[r].im} : cmul(x[r], q);
+    }
+}
+
+template <typename R, int G, int P>
+__device__ __forceinline__ void trial_at(uint32_t type, uint32_t form, uint32_t neg_val,
+                                         const cplx<R> (&u)[4], uint32_t rm, uint32_t rv,
+                                         cplx<R> (&x)[1 << G])
+{
+    if (type == kOpSwap) {
+        if (rm == 0)
+            trial_swap<R, G, P, false>(rm, rv, x);
+        else
+            trial_swap<R, G, P, true>(rm, rv, x);
+        return;
+    }
+    if (type == kOpDiag || type == kOpNeg) {
+        trial_phase<R, G, P>(type == kOpNeg, type == kOpNeg ? neg_val : 1u, u[3], rm, rv, x);
+        return;
+    }
+    if (rm != 0) {
+        if (form == 3)
+            trial_pair<R, G, P, 3, false>(u, 0, 0, x);  // not produced by the gate set
+        else
+            trial_pair<R, G, P, 1, true>(u, rm, rv, x);
+        return;
+    }
+    switch (form) {
+    case 0: trial_pair<R, G, P, 0, false>(u, rm, rv, x); break;
+    case 1: trial_pair<R, G, P, 1, false>(u, rm, rv, x); break;
+    case 2: trial_pair<R, G, P, 2, false>(u, rm, rv, x); break;
+    default: trial_pair<R, G, P, 3, false>(u, rm, rv, x); break;
+    }
+}
+
+// One trial operation on the thread's registers (base index j0).  The
+// record's fields are uniform and read with scalar loads.
+template <typename R, int G>
+__device__ __forceinline__ void trial_apply(const TrialGateOp<R> &op, uint32_t j0,
+                                            cplx<R> (&x)[1 << G])
+{
+    const uint32_t meta = op.meta, regs = op.regs;
+    const uint32_t type = meta & 15u, form = (meta >> 4) & 15u, neg_val = (meta >> 8) & 1u;
+    const uint32_t P = (meta >> 12) & 15u;
+    const uint32_t rm = regs & 255u, rv = (regs >> 8) & 255u, rz = (regs >> 16) & 255u;
+    const uint32_t zmask = op.zmask;
+    if ((j0 & op.lm) == op.lv) {
+        cplx<R> u[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            u[k] = op.u[k];
+        switch (P) {
+        case 0: trial_at<R, G, 0>(type, form, neg_val, u, rm, rv, x); break;
+        case 1: trial_at<R, G, 1>(type, form, neg_val, u, rm, rv, x); break;
+        case 2: trial_at<R, G, 2>(type, form, neg_val, u, rm, rv, x); break;
+        case 3: if constexpr (G > 3) trial_at<R, G, 3>(type, form, neg_val, u, rm, rv, x); break;
+        case 4: if constexpr (G > 4) trial_at<R, G, 4>(type, form, neg_val, u, rm, rv, x); break;
+        default: {
+            // a diagonal or sign flip on a qubit that is not a group qubit:
+            // the thread's bit of it decides, for all of its registers
+            const uint32_t target = (meta >> 16) & 31u;
+            const bool neg = type == kOpNeg;
+            if (((j0 >> target) & 1u) == (neg ? neg_val : 1u)) {
+#pragma unroll
+                for (int r = 0; r < (1 << G); ++r)
+                    if (((uint32_t)r & rm) == rv)
+                        x[r] = neg ? cplx<R>{-x[r].re, -x[r].im} : cmul(x[r], u[3]);
+            }
+            break;
+        }
+        }
+    }
+    if ((zmask | rz) != 0) {
+        const uint32_t lpar = __popc(j0 & zmask) & 1u;
+#pragma unroll
+        for (int r = 0; r < (1 << G); ++r)
+            if ((lpar ^ (__popc((uint32_t)r & rz) & 1u)) != 0)
+                x[r] = {-x[r].re, -x[r].im};
+    }
+}
+
+// Preparation of the register-group variants: one workgroup per trial of
+// the batch builds all of the trial's gates (draws, X mask, matrices in
+// FP64) into global memory, and the X mask after the last gate, so that the
+// trial kernel itself does no FP64 work and reads each gate with scalar
+// loads.
+constexpr int kPrepThreads = 256;
+
+template <typename R>
+__global__ void __launch_bounds__(kPrepThreads) k_trial_prep(const TrialLaunch L, uint64_t t0,
+                                                             const uint32_t *__restrict__ gword,
+                                                             TrialGateOp<R> *__restrict__ out,
+                                                             uint32_t *__restrict__ out_X)
+{
+    __shared__ uint32_t scan[kPrepThreads];
+    const uint32_t tid = threadIdx.x, n = L.ngates, M = L.M;
+    const uint64_t t = t0 + blockIdx.x;  // trial index within the call
+    const uint64_t trial = L.trial0 + t;
+    const bool draws_flip = L.p_bit > 0.0 || L.p_phase > 0.0;
+    const uint64_t thr_b = flip_threshold(L.p_bit), thr_p = flip_threshold(L.p_phase);
+    const int G = L.variant == 2 ? 4 : 5;
+    TrialGateOp<R> *ops = out + (uint64_t)blockIdx.x * n;
+    uint32_t X = 0;  // bit flips before the current block of gates
+    for (uint32_t c0 = 0; c0 < n; c0 += kPrepThreads) {
+        const uint32_t g = c0 + tid;
+        uint32_t bm = 0, zm = 0;
+        if (g < n && draws_flip) {
+            for (uint32_t q = 0; q < M; ++q) {
+                const u64x4 r = philox4x64_10(g, q, kStreamFlip, 0, L.seed, trial);
+                if ((r.w[0] >> 32) < thr_b)
+                    bm |= 1u << q;
+                if ((r.w[1] >> 32) < thr_p)
+                    zm |= 1u << q;
+            }
+        }
+        // inclusive XOR scan of the block's bit flips
+        scan[tid] = bm;
+        __syncthreads();
+        for (uint32_t off = 1; off < kPrepThreads; off <<= 1) {
+            const uint32_t v = tid >= off ? scan[tid - off] : 0u;
+            __syncthreads();
+            scan[tid] ^= v;
+            __syncthreads();
+        }
+        const uint32_t xg = X ^ scan[tid] ^ bm;  // mask before gate g
+        if (g < n) {
+            const TrialGate gd = L.gates[g];
+            const double eps = L.sigma > 0.0 ? L.sigma * step_gaussian(L.seed, trial, g) : 0.0;
+            uint32_t type;
+            double u[8];
+            gate_matrix(gd.kind, gd.theta, eps, type, u);
+            const bool flipped = (xg >> gd.target) & 1u;
+            if (flipped) {
+                // X U X: swap rows and columns
+                for (int k = 0; k < 2; ++k) {
+                    double a = u[k];
+                    u[k] = u[6 + k];
+                    u[6 + k] = a;
+                    a = u[2 + k];
+                    u[2 + k] = u[4 + k];
+                    u[4 + k] = a;
+                }
+            }
+            if (type == kOpDiag) {
+                // diag(d0, d1) = d0 diag(1, d1 / d0); d0 is a global phase
+                const double n0 = u[0] * u[0] + u[1] * u[1];
+                const double qr = (u[6] * u[0] + u[7] * u[1]) / n0;
+                const double qi = (u[7] * u[0] - u[6] * u[1]) / n0;
+                u[0] = 1.0; u[1] = 0.0; u[6] = qr; u[7] = qi;
+            }
+            TrialGateOp<R> op;
+            op.u[0] = {(R)u[0], (R)u[1]};
+            op.u[1] = {(R)u[2], (R)u[3]};
+            op.u[2] = {(R)u[4], (R)u[5]};
+            op.u[3] = {(R)u[6], (R)u[7]};
+            const bool real_off = u[3] == 0.0 && u[5] == 0.0;
+            const bool real_diag = u[1] == 0.0 && u[7] == 0.0;
+            const bool zero_diag = u[0] == 0.0 && u[6] == 0.0;
+            const uint32_t form = !real_off ? 3u : real_diag ? 0u : zero_diag ? 2u : 1u;
+            // positions relative to the gate's group
+            const uint32_t w = gword[g];
+            const uint32_t cval = gd.cmask & ~xg;
+            uint32_t P = 15, rm = 0, rv = 0, rz = 0, gmask = 0;
+            for (int i = 0; i < G; ++i) {
+                const uint32_t b = (w >> (4 * i)) & 15u;
+                gmask |= 1u << b;
+                if (b == gd.target)
+                    P = (uint32_t)i;
+                rm |= ((gd.cmask >> b) & 1u) << i;
+                rv |= ((cval >> b) & 1u) << i;
+                rz |= ((zm >> b) & 1u) << i;
+            }
+            // a lane-space mask lists its qubits in the thread's base index,
+            // which keeps the group qubits at zero: the masks are used as is
+            op.meta = type | (form << 4) | ((flipped ? 0u : 1u) << 8) | (P << 12) |
+                      (gd.target << 16);
+            op.regs = rm | (rv << 8) | (rz << 16);
+            op.lm = gd.cmask & ~gmask;
+            op.lv = cval & ~gmask;
+            // phase flips follow this step's bit flips; Z_q on the true
+            // register is Z_q on the stored one up to a global sign
+            op.zmask = zm & ~gmask;
+            op.pad[0] = op.pad[1] = op.pad[2] = 0;
+            ops[g] = op;
+        }
+        X ^= scan[kPrepThreads - 1];
+        __syncthreads();
+    }
+    if (tid == 0)
+        out_X[blockIdx.x] = X;
+}
+
+// LDS slot of register element j: one pad slot after every 128 bytes, so
+// that lanes striding over a power of two of elements spread over the banks.
+template <typename R>
+__device__ __forceinline__ uint32_t trial_slot(uint32_t j)
+{
+    return j + (j >> (sizeof(cplx<R>) == 8 ? 4 : 3));
+}
+
+template <typename R>
+size_t trial_group_lds(int M)
+{
+    const size_t n = (size_t)1 << M;
+    return (n + (n >> (sizeof(cplx<R>) == 8 ? 4 : 3))) * sizeof(cplx<R>);
+}
+
+// The gate records, the group records and the masks are read-only here and
+// alias nothing the kernel writes, so their uniform reads become scalar
+// loads.
+template <typename R, int G, int T>
+__global__ void __launch_bounds__(T) k_trials_groups(const TrialLaunch L, uint64_t t0,
+                                                     uint64_t nt,
+                                                     const TrialGateOp<R> *__restrict__ ops,
+                                                     const uint32_t *__restrict__ Xs,
+                                                     const uint32_t *__restrict__ groups,
+                                                     const cplx<R> *__restrict__ ideal,
+                                                     double *__restrict__ out_F)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    cplx<R> *buf = reinterpret_cast<cplx<R> *>(lds);
+    __shared__ double red[4][T / 64];
+    const uint32_t tid = threadIdx.x, n = L.ngates;
+
+    for (uint64_t b = blockIdx.x; b < nt; b += gridDim.x) {
+        const TrialGateOp<R> *tops = ops + b * n;
+        uint32_t w = L.ngroups > 0 ? groups[2] : 0u;
+        uint32_t j0, gmask;
+        trial_layout<G>(w, j0, gmask);
+        cplx<R> x[1 << G];
+#pragma unroll
+        for (int r = 0; r < (1 << G); ++r)
+            x[r] = {R((r == 0 && j0 == 0) ? 1 : 0), R(0)};
+        for (uint32_t gi = 0; gi < L.ngroups; ++gi) {
+            const uint32_t first = groups[4 * gi], count = groups[4 * gi + 1];
+            const uint32_t nw = groups[4 * gi + 2];
+            if (nw != w) {
+                // registers -> LDS in the old layout, LDS -> registers in the new one
+#pragma unroll
+                for (int r = 0; r < (1 << G); ++r)
+                    buf[trial_slot<R>(trial_index<G>(j0, w, r))] = x[r];
+                __syncthreads();
+                w = nw;
+                trial_layout<G>(w, j0, gmask);
+#pragma unroll
+                for (int r = 0; r < (1 << G); ++r)
+                    x[r] = buf[trial_slot<R>(trial_index<G>(j0, w, r))];
+                __syncthreads();
+            }
+            for (uint32_t g = first; g < first + count; ++g)
+                trial_apply<R, G>(tops[g], j0, x);
+        }
+        // fidelity against the error-free register, reading psi(i) = s(i ^ X)
+        const uint32_t X = Xs[b];
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int r = 0; r < (1 << G); ++r) {
+            const uint32_t j = trial_index<G>(j0, w, r);
+            const cplx<R> a = ideal[j ^ X];
+            const double ar = a.re, ai = a.im, br = x[r].re, bi = x[r].im;
+            v[0] += ar * br + ai * bi;
+            v[1] += ar * bi - ai * br;
+            v[2] += ar * ar + ai * ai;
+            v[3] += br * br + bi * bi;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            v[c] = wave_sum(v[c]);
+        __syncthreads();
+        if ((tid & 63) == 0) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                red[c][tid >> 6] = v[c];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int wv = 0; wv < T / 64; ++wv)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    s4[c] += red[c][wv];
+            out_F[t0 + b] = (s4[0] * s4[0] + s4[1] * s4[1]) / (s4[2] * s4[3]);
+        }
+    }
+}
+
 template <typename R, int T>
 hipError_t launch_t(const TrialLaunch &L, hipStream_t st)
 {
@@ -268,6 +703,87 @@ hipError_t launch_t(const TrialLaunch &L, hipStream_t st)
     return hipGetLastError();
 }
 
+template <typename R, int G, int T>
+hipError_t launch_g(const TrialLaunch &L, hipStream_t st)
+{
+    const size_t lds = trial_group_lds<R>((int)L.M);
+    auto fn = k_trials_groups<R, G, T>;
+    static size_t lds_allowed = 65536;  // per instantiation
+    if (lds > lds_allowed) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
+        lds_allowed = lds;
+    }
+    TrialGateOp<R> *ops = reinterpret_cast<TrialGateOp<R> *>(L.prep_ops);
+    for (uint64_t t0 = 0; t0 < L.n_trials; t0 += L.prep_batch) {
+        const uint64_t nt = std::min<uint64_t>(L.prep_batch, L.n_trials - t0);
+        hipLaunchKernelGGL(k_trial_prep<R>, dim3((unsigned)nt), dim3(kPrepThreads), 0, st, L, t0,
+                           L.sched + 4 * (L.nchunks + L.ngroups), ops, L.prep_X);
+        const uint64_t grid = nt < (uint64_t)L.grid ? nt : (uint64_t)L.grid;
+        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(T), lds, st, L, t0, nt,
+                           (const TrialGateOp<R> *)ops, (const uint32_t *)L.prep_X,
+                           L.sched + 4 * L.nchunks, reinterpret_cast<const cplx<R> *>(L.ideal),
+                           L.out_F);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+template <typename R, int G>
+hipError_t launch_groups(const TrialLaunch &L, hipStream_t st)
+{
+    if (L.sched == nullptr || L.prep_ops == nullptr || L.prep_X == nullptr || L.prep_batch == 0 ||
+        (int)L.M - G < 6 || (int)L.M - G > 10)
+        return hipErrorInvalidValue;
+    switch ((int)L.M - G) {
+    case 6: return launch_g<R, G, 64>(L, st);
+    case 7: return launch_g<R, G, 128>(L, st);
+    case 8: return launch_g<R, G, 256>(L, st);
+    case 9: return launch_g<R, G, 512>(L, st);
+    default: return launch_g<R, G, 1024>(L, st);
+    }
+}
+
+template <typename R, int G, int T>
+int grid_g(int M)
+{
+    const size_t lds = trial_group_lds<R>(M);
+    auto fn = k_trials_groups<R, G, T>;
+    if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, T, lds) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * cus;
+}
+
+template <typename R, int G>
+int grid_groups(int M)
+{
+    switch (M - G) {
+    case 6: return grid_g<R, G, 64>(M);
+    case 7: return grid_g<R, G, 128>(M);
+    case 8: return grid_g<R, G, 256>(M);
+    case 9: return grid_g<R, G, 512>(M);
+    case 10: return grid_g<R, G, 1024>(M);
+    default: return 0;
+    }
+}
+
 }  // namespace
 
 size_t trial_lds_bytes(int M, int elem_bytes)
@@ -276,18 +792,28 @@ size_t trial_lds_bytes(int M, int elem_bytes)
     return ((size_t)1 << M) * (size_t)elem_bytes + kChunk * op_bytes;
 }
 
-// Variants the autotuner chooses from: workgroup size 1024 or 512.
+// Variants the autotuner chooses from: one LDS sweep per gate with 1024 or
+// 512 threads, or the register in registers with 4 or 5 group qubits.
 template <typename R>
 hipError_t launch_trials(const TrialLaunch &L, hipStream_t st)
 {
     switch (L.variant) {
     case 0: return launch_t<R, 1024>(L, st);
     case 1: return launch_t<R, 512>(L, st);
+    case 2: return launch_groups<R, 4>(L, st);
+    case 3: return launch_groups<R, 5>(L, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-int trial_variants() { return 2; }
+int trial_variants() { return 4; }
+
+int trial_group_bits(int variant) { return variant == 2 ? 4 : variant == 3 ? 5 : 0; }
+
+size_t trial_gate_op_bytes(int elem_bytes)
+{
+    return elem_bytes == 8 ? sizeof(TrialGateOp<float>) : sizeof(TrialGateOp<double>);
+}
 
 template <typename R, int T>
 int grid_t(int M)
@@ -312,14 +838,25 @@ int grid_t(int M)
 
 int trial_grid(int variant, int M, int elem_bytes)
 {
-    if (elem_bytes == 8)
-        return variant == 0 ? grid_t<float, 1024>(M) : grid_t<float, 512>(M);
-    return variant == 0 ? grid_t<double, 1024>(M) : grid_t<double, 512>(M);
+    const bool f = elem_bytes == 8;
+    switch (variant) {
+    case 0: return f ? grid_t<float, 1024>(M) : grid_t<double, 1024>(M);
+    case 1: return f ? grid_t<float, 512>(M) : grid_t<double, 512>(M);
+    case 2: return f ? grid_groups<float, 4>(M) : grid_groups<double, 4>(M);
+    case 3: return f ? grid_groups<float, 5>(M) : grid_groups<double, 5>(M);
+    default: return 0;
+    }
 }
 
 const char *trial_variant_name(int v)
 {
-    return v == 0 ? "lds-per-gate-1024" : v == 1 ? "lds-per-gate-512" : "?";
+    switch (v) {
+    case 0: return "lds-per-gate-1024";
+    case 1: return "lds-per-gate-512";
+    case 2: return "register-groups-4";
+    case 3: return "register-groups-5";
+    default: return "?";
+    }
 }
 
 template hipError_t launch_trials<float>(const TrialLaunch &, hipStream_t);

@@ -74,8 +74,24 @@ struct TrialLaunch {
     double *out_F;            // device, n_trials
     int variant;              // schedule chosen by the autotuner
     int grid;                 // persistent workgroup count
+    // register-group variants: device array of nchunks chunk records
+    // {first gate, gates, first group, groups} (none at present), ngroups
+    // group records {first gate, gates, qubit word, 0}, then the qubit word
+    // of each gate's group
+    const uint32_t *sched;
+    uint32_t nchunks, ngroups;
+    // ...and their per-trial gates, built by a preparation kernel for
+    // prep_batch trials at a time: prep_ops holds prep_batch * ngates records
+    // of trial_gate_op_bytes each, prep_X prep_batch masks
+    void *prep_ops;
+    uint32_t *prep_X;
+    uint64_t prep_batch;
 };
+size_t trial_gate_op_bytes(int elem_bytes);
+// LDS of the sweep variants (register plus a chunk of built gates).
 size_t trial_lds_bytes(int M, int elem_bytes);
+// Group qubits of a register-group variant (0 for the LDS-sweep variants).
+int trial_group_bits(int variant);
 template <typename R>
 hipError_t launch_trials(const TrialLaunch &L, hipStream_t st);
 int trial_variants();

@@ -85,14 +85,93 @@ void tune_store(const TuneKey &k, int v)
     fclose(f);
 }
 
+// Register-group schedule of a circuit (variants with G group qubits):
+// groups of consecutive gates whose non-diagonal targets (every kind but Rz
+// and Z) span at most G qubits, each padded to G qubits with the qubits its
+// diagonal gates act on (most used first; on a group qubit a diagonal is a
+// per-register factor) and then the highest free qubits.  out = the group
+// records (see TrialLaunch; no chunk records), then each gate's group word.
+void group_schedule(const qsim_gate *gates, size_t n, int M, int G, std::vector<uint32_t> &out,
+                    uint32_t &nchunks, uint32_t &ngroups)
+{
+    auto diagonal = [](const qsim_gate &g) { return g.kind == QSIM_RZ || g.kind == QSIM_Z; };
+    out.clear();
+    ngroups = 0;
+    size_t i = 0;
+    while (i < n) {
+        uint32_t cur = 0;  // qubit mask of the group's non-diagonal targets
+        size_t j = i;
+        while (j < n) {
+            if (!diagonal(gates[j])) {
+                const uint32_t tb = 1u << gates[j].target;
+                if (!(cur & tb)) {
+                    if (__builtin_popcount(cur) == G)
+                        break;
+                    cur |= tb;
+                }
+            }
+            ++j;
+        }
+        int uses[32] = {0};
+        for (size_t k = i; k < j; ++k)
+            if (diagonal(gates[k]))
+                ++uses[gates[k].target];
+        while (__builtin_popcount(cur) < G) {
+            int best = -1;
+            for (int q = 0; q < M; ++q)
+                if (uses[q] > 0 && !((cur >> q) & 1u) && (best < 0 || uses[q] > uses[best]))
+                    best = q;
+            if (best < 0)
+                break;
+            cur |= 1u << best;
+        }
+        for (int q = M - 1; q >= 0 && __builtin_popcount(cur) < G; --q)
+            cur |= 1u << q;
+        uint32_t word = 0;
+        int slot = 0;
+        for (int q = 0; q < M; ++q)
+            if ((cur >> q) & 1u)
+                word |= (uint32_t)q << (4 * slot++);
+        out.insert(out.end(), {(uint32_t)i, (uint32_t)(j - i), word, 0u});
+        ++ngroups;
+        i = j;
+    }
+    for (uint32_t gi = 0; gi < ngroups; ++gi)
+        for (uint32_t k = 0; k < out[4 * gi + 1]; ++k)
+            out.push_back(out[4 * gi + 2]);
+    nchunks = 0;
+}
+
+// The register-group schedules on the device, one per group size.
+struct GroupSched {
+    DevBuf buf[2];  // G = 4, 5
+    uint32_t nchunks[2] = {0, 0}, ngroups[2] = {0, 0};
+    void apply(TrialLaunch &L, int variant) const
+    {
+        const int G = trial_group_bits(variant);
+        if (G < 4 || G > 5 || buf[G - 4].p == nullptr) {
+            L.sched = nullptr;
+            L.nchunks = L.ngroups = 0;
+            return;
+        }
+        L.sched = reinterpret_cast<const uint32_t *>(buf[G - 4].p);
+        L.nchunks = nchunks[G - 4];
+        L.ngroups = ngroups[G - 4];
+    }
+};
+
 hipError_t launch(int dtype, const TrialLaunch &L, hipStream_t st)
 {
     return dtype == QSIM_C64 ? launch_trials<float>(L, st) : launch_trials<double>(L, st);
 }
 
 // Time every variant on one round of trials (one trial per workgroup) and
-// keep the fastest.  The timing runs write to a scratch output.
-int autotune(int dtype, TrialLaunch L, hipStream_t st, double *scratch, int &best)
+// keep the fastest.  The timing runs write to a scratch output of
+// kTuneTrials doubles.
+constexpr int kTuneTrials = 4096;
+
+int autotune(int dtype, TrialLaunch L, const GroupSched &gs, hipStream_t st, double *scratch,
+             int &best)
 {
     best = -1;
     float best_ms = 0.f;
@@ -112,7 +191,10 @@ int autotune(int dtype, TrialLaunch L, hipStream_t st, double *scratch, int &bes
             continue;
         L.variant = v;
         L.grid = grid;
-        L.n_trials = (uint64_t)grid;
+        L.n_trials = (uint64_t)std::min(grid, kTuneTrials);
+        gs.apply(L, v);
+        if (trial_group_bits(v) > 0 && L.sched == nullptr)
+            continue;
         L.out_F = scratch;
         // once to warm up, once timed
         e = launch(dtype, L, st);
@@ -223,8 +305,40 @@ extern "C" int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits,
     if (n > 0 && (e = hipMemcpyAsync(dg.p, hg.data(), n * sizeof(TrialGate),
                                      hipMemcpyHostToDevice, st)) != hipSuccess)
         return hip_err(e, "gate upload");
+    // register-group schedules (variants 2 and 3), where the register fits
+    GroupSched gs;
+    std::vector<uint32_t> sched[2];
+    for (int G = 4; G <= 5; ++G) {
+        if (n == 0 || num_qubits - G < 6 || num_qubits - G > 10)
+            continue;
+        group_schedule(gates, n, num_qubits, G, sched[G - 4], gs.nchunks[G - 4],
+                       gs.ngroups[G - 4]);
+        const size_t bytes = sched[G - 4].size() * sizeof(uint32_t);
+        if ((e = hipMalloc(&gs.buf[G - 4].p, bytes)) != hipSuccess)
+            return hip_err(e, "schedule buffer");
+        if ((e = hipMemcpyAsync(gs.buf[G - 4].p, sched[G - 4].data(), bytes,
+                                hipMemcpyHostToDevice, st)) != hipSuccess)
+            return hip_err(e, "schedule upload");
+    }
+
+    // per-trial gate records of the register-group variants, a batch of
+    // trials at a time (at most ~256 MiB)
+    DevBuf dprep, dprepx;
+    uint64_t batch = 0;
+    if (gs.buf[0].p != nullptr || gs.buf[1].p != nullptr) {
+        const size_t per_trial = n * trial_gate_op_bytes(dtype == QSIM_C64 ? 8 : 16);
+        const uint64_t cap = std::max<uint64_t>(1, ((size_t)256 << 20) / per_trial);
+        batch = std::min<uint64_t>(cap, std::max<uint64_t>(n_trials, (uint64_t)kTuneTrials));
+        if ((e = hipMalloc(&dprep.p, batch * per_trial)) != hipSuccess)
+            return hip_err(e, "trial gate buffer");
+        if ((e = hipMalloc(&dprepx.p, batch * sizeof(uint32_t))) != hipSuccess)
+            return hip_err(e, "trial mask buffer");
+    }
 
     TrialLaunch L{};
+    L.prep_ops = dprep.p;
+    L.prep_X = reinterpret_cast<uint32_t *>(dprepx.p);
+    L.prep_batch = batch;
     L.gates = reinterpret_cast<const TrialGate *>(dg.p);
     L.ngates = (uint32_t)n;
     L.M = (uint32_t)num_qubits;
@@ -246,12 +360,21 @@ extern "C" int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits,
             variant = it->second;
     }
     const int elem = dtype == QSIM_C64 ? 8 : 16;
+    // QSIM_TRIAL_VARIANT forces a variant (when it can run this register)
+    if (const char *v = getenv("QSIM_TRIAL_VARIANT")) {
+        const int forced = atoi(v);
+        TrialLaunch probe = L;
+        gs.apply(probe, forced);
+        if (forced >= 0 && forced < trial_variants() && trial_grid(forced, num_qubits, elem) > 0 &&
+            (trial_group_bits(forced) == 0 || probe.sched != nullptr))
+            variant = forced;
+    }
     if (variant < 0 || trial_grid(variant, num_qubits, elem) <= 0) {
-        if ((e = hipMalloc(&dscratch.p, 4096 * sizeof(double))) != hipSuccess)
+        if ((e = hipMalloc(&dscratch.p, kTuneTrials * sizeof(double))) != hipSuccess)
             return hip_err(e, "tune buffer");
         TrialLaunch T = L;
         T.n_trials = 1;  // grid set per variant inside
-        rc = autotune(dtype, T, st, reinterpret_cast<double *>(dscratch.p), variant);
+        rc = autotune(dtype, T, gs, st, reinterpret_cast<double *>(dscratch.p), variant);
         if (rc != QSIM_OK)
             return rc;
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -259,6 +382,7 @@ extern "C" int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits,
     }
     L.variant = variant;
     L.grid = trial_grid(variant, num_qubits, elem);
+    gs.apply(L, variant);
     if (L.grid <= 0)
         return set_error(QSIM_EDEVICE, "trial kernel cannot run this register");
     L.n_trials = n_trials;

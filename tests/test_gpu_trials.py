@@ -93,3 +93,22 @@ def test_trials_reject_bad_input():
     with pytest.raises(q.QsimError):
         q.qsim_run_trials(cg.gates_from_list([(cg.CNOT, 1, 1)]), 6, q.QSIM_C64, 0.1, 0, 0, 0, 0, 4)
     assert len(q.qsim_run_trials(g, 6, q.QSIM_C64, 0.1, 0, 0, 0, 0, 0)) == 0
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("M", [11, 12])
+@pytest.mark.parametrize("dtype,tol", [(q.QSIM_C128, 1e-12), (q.QSIM_C64, 1e-6)])
+def test_every_kernel_variant_matches_oracle(monkeypatch, variant, M, dtype, tol):
+    """Each variant the autotuner picks from (one LDS sweep per gate with 1024
+    or 512 threads; the register in registers with 4 or 5 group qubits),
+    forced in turn, against the oracle with dense flips and controls."""
+    print(f"trials variant={variant} M={M} dtype={dtype}", flush=True)
+    monkeypatch.setenv("QSIM_TRIAL_VARIANT", str(variant))
+    gates = cg.random_circuit(M, 300, 40 + M,
+                              kinds=(cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT, cg.TOFFOLI))
+    em = oracle.Errors(sigma=0.05, p_bitflip=0.004, p_phaseflip=0.004, seed=17 + M, trial=3)
+    want = oracle.run_trials(gates, M, em, 12)
+    got = q.qsim_run_trials(gates, M, dtype, em.sigma, em.p_bitflip, em.p_phaseflip, em.seed,
+                            em.trial, 12)
+    assert np.max(np.abs(got - want)) < tol, np.max(np.abs(got - want))
+    assert np.mean(want < 0.9) > 0.3
