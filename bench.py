@@ -19,7 +19,9 @@ launch; algorithmic bytes 2 x 8 x 2^30 and algorithmic flops per launch, and
 the ceiling its arithmetic intensity puts it under), the FP64 oracle timed on
 a bounded sample on the host cores, batched Monte Carlo trials/s (M=14, 500
 gates, 4096 trials, one launch), and the serving loop's p50/p99 latency and
-throughput on a Poisson trace against the same trace served sequentially.
+throughput on a Poisson trace against the same trace served sequentially,
+and the 64 GiB registers (M=33 complex64, M=32 complex128): fused-pass HBM
+rate and the complex64 error against complex128.
 """
 from __future__ import annotations
 
@@ -103,6 +105,46 @@ def bench_mc(q, cg, np):
     return {"value": T / dt, "unit": "trials/s", "trials": T, "num_qubits": Mm, "gates": Gm,
             "ms": dt * 1e3, "fidelity_mean": float(F.mean()), "fidelity_var": float(F.var()),
             "fidelity_hist_10bins": hist.tolist()}
+
+
+def bench_large(q, cg, np):
+    """Large registers (64 GiB): M=33 complex64 and M=32 complex128, a
+    500-gate circuit with half of the targets on the top 4 qubits, sigma =
+    1e-3.  Fused-pass HBM rate of each, and the complex64 register's error
+    against the complex128 one at M=33 (192 GiB on the device at once)."""
+    out = {"gates": 500, "top_bias": 0.5, "sigma": SIGMA}
+    for Ml, dt, name in ((33, q.QSIM_C64, "m33_c64"), (32, q.QSIM_C128, "m32_c128")):
+        gates = cg.random_circuit(Ml, 500, Ml, top_bias=0.5)
+        try:
+            with q.State(Ml, dt) as s:
+                s.inject_errors(SIGMA, 0.0, 0.0, seed=1000 + Ml, trial=0)
+                s.apply(gates[:20])
+                s.synchronize()
+                s.profile(True)
+                t0 = time.perf_counter()
+                s.apply(gates)
+                s.synchronize()
+                wall = time.perf_counter() - t0
+                st = s.stats()
+        except q.QsimError as e:
+            out[name] = {"error": str(e)}
+            continue
+        gbs = st["fused_bytes"] / (st["fused_ms"] * 1e-3) / 1e9 if st["fused_ms"] > 0 else None
+        out[name] = {"amplitude_updates_per_s": 500 * float(1 << Ml) / wall,
+                     "fused_passes": st["fused_passes"], "fused_GBps": gbs,
+                     "hbm_frac": gbs / HBM_PEAK_GBS if gbs else None,
+                     "ms": wall * 1e3}
+    # complex64 error at M=33, measured against complex128 on the device
+    gates = cg.random_circuit(33, 500, 33, top_bias=0.5)
+    try:
+        with q.State(33, q.QSIM_C64) as a, q.State(33, q.QSIM_C128) as b:
+            for s in (a, b):
+                s.inject_errors(SIGMA, 0.0, 0.0, seed=1033, trial=0)
+                s.apply(gates)
+            out["m33_c64_infidelity_vs_c128"] = 1.0 - a.fidelity(b)
+    except q.QsimError as e:
+        out["m33_c64_infidelity_vs_c128"] = {"error": str(e)}
+    return out
 
 
 def bench_serving(q, cg, np, n_req: int = 80):
@@ -255,6 +297,9 @@ def main() -> int:
     serving = bench_serving(q, cg, np)
     log(f"bench: serving p99 {serving['continuous_batching']['p99_ms']:.1f} ms "
         f"(sequential {serving['sequential']['p99_ms']:.1f} ms)")
+    log("bench: 64 GiB registers")
+    large = bench_large(q, cg, np)
+    log(f"bench: large registers {json.dumps(large)}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -300,6 +345,7 @@ def main() -> int:
                               "algorithmic_GBps": plain_gbs, "gates": 200},
             "mc_trials": mc,
             "serving": serving,
+            "large_register": large,
         },
     }
     print(json.dumps(out), flush=True)
