@@ -445,8 +445,53 @@ OpUse op_use(const Op &op)
 // mode stops the scan at the first operation it cannot take instead, so
 // passes are runs of the stream.  Every pass takes at least the first
 // operation left (it commutes with nothing earlier and the set has room).
+// Reorder the operations of one fused pass, order[first, first + count), so
+// that they fall into few register groups (each group is one LDS
+// re-partition of the tile): repeatedly take, in order, every operation that
+// commutes with the operations left behind and whose target fits a set of at
+// most G qubits (uncontrolled diagonals fit any set).
+void cluster_pass(const std::vector<Op> &ops, std::vector<uint32_t> &order, size_t first,
+                  size_t count, int G)
+{
+    std::vector<uint32_t> rem(order.begin() + (std::ptrdiff_t)first,
+                              order.begin() + (std::ptrdiff_t)(first + count));
+    std::vector<uint32_t> left, out;
+    out.reserve(count);
+    while (!rem.empty()) {
+        uint64_t cur = 0, bx = 0, bz = 0;
+        int ncur = 0;
+        left.clear();
+        for (const uint32_t idx : rem) {
+            const Op &op = ops[idx];
+            const OpUse u = op_use(op);
+            bool ok = (u.x & (bx | bz)) == 0 && (u.z & bx) == 0;
+            if (ok && needs_tile_target(op)) {
+                const uint64_t tb = 1ull << op.target;
+                if (!(cur & tb)) {
+                    if (ncur == G) {
+                        ok = false;
+                    } else {
+                        cur |= tb;
+                        ++ncur;
+                    }
+                }
+            }
+            if (ok) {
+                out.push_back(idx);
+            } else {
+                left.push_back(idx);
+                bx |= u.x;
+                bz |= u.z;
+            }
+        }
+        rem.swap(left);
+    }
+    std::copy(out.begin(), out.end(), order.begin() + (std::ptrdiff_t)first);
+}
+
 void schedule_fused(const qsim_state *s, const std::vector<Op> &ops, size_t lo, size_t hi, int k,
-                    bool reorder, std::vector<uint32_t> &order, std::vector<PassPlan> &plan)
+                    int G, bool reorder, std::vector<uint32_t> &order,
+                    std::vector<PassPlan> &plan)
 {
     const int low = std::min(s->low_bits, k);
     std::vector<uint32_t> rem, left;
@@ -488,6 +533,8 @@ void schedule_fused(const qsim_state *s, const std::vector<Op> &ops, size_t lo, 
             bz |= u.z;
         }
         plan.push_back({true, first, taken, false});
+        if (reorder)
+            cluster_pass(ops, order, first, taken, G);
         rem.swap(left);
     }
 }
@@ -519,13 +566,13 @@ void schedule(const qsim_state *s, const std::vector<Op> &ops, std::vector<uint3
         size_t lo = 0;
         for (size_t i = 0; i < n; ++i) {
             if (!fusable(ops[i])) {
-                schedule_fused(s, ops, lo, i, k, reorder, order, plan);
+                schedule_fused(s, ops, lo, i, k, G, reorder, order, plan);
                 order.push_back((uint32_t)i);
                 plan.push_back({false, order.size() - 1, 1, false});
                 lo = i + 1;
             }
         }
-        schedule_fused(s, ops, lo, n, k, reorder, order, plan);
+        schedule_fused(s, ops, lo, n, k, G, reorder, order, plan);
     }
     // renormalisation points
     std::vector<bool> ran(n, false);
