@@ -301,8 +301,8 @@ __global__ void __launch_bounds__(T) k_trials(const TrialGate *gates, uint32_t n
 // targets fall on at most G qubits; inside a group every gate is a fixed
 // pattern of register pairs (a diagonal on another qubit is a per-thread
 // factor), and between groups with different qubits the register is
-// re-partitioned through LDS.  Gates are built per chunk of whole groups.
-
+// re-partitioned through LDS.  Every trial's gates are built beforehand by
+// a preparation kernel (below) and read with scalar loads.
 
 // Qubit i of a group word (G <= 5 qubits < 16, four bits each, ascending).
 __device__ __forceinline__ uint32_t gq(uint32_t w, int i) { return (w >> (4 * i)) & 15u; }
