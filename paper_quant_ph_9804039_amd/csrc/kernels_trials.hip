@@ -391,6 +391,14 @@ template <typename R, int G, int P>
 __device__ __forceinline__ void trial_phase(bool neg, uint32_t on, cplx<R> q, uint32_t rm,
                                             uint32_t rv, cplx<R> (&x)[1 << G])
 {
+    if (!neg && rm == 0) {
+        // an uncontrolled phase (Rz): half of the registers move
+#pragma unroll
+        for (int r = 0; r < (1 << G); ++r)
+            if ((r >> P) & 1)
+                x[r] = cmul(x[r], q);
+        return;
+    }
 #pragma unroll
     for (int r = 0; r < (1 << G); ++r) {
         if ((((uint32_t)r >> P) & 1u) != on || ((uint32_t)r & rm) != rv)
@@ -458,10 +466,16 @@ __device__ __forceinline__ void trial_apply(const TrialGateOp<R> &op, uint32_t j
             const uint32_t target = (meta >> 16) & 31u;
             const bool neg = type == kOpNeg;
             if (((j0 >> target) & 1u) == (neg ? neg_val : 1u)) {
+                if (!neg && rm == 0) {
 #pragma unroll
-                for (int r = 0; r < (1 << G); ++r)
-                    if (((uint32_t)r & rm) == rv)
-                        x[r] = neg ? cplx<R>{-x[r].re, -x[r].im} : cmul(x[r], u[3]);
+                    for (int r = 0; r < (1 << G); ++r)
+                        x[r] = cmul(x[r], u[3]);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < (1 << G); ++r)
+                        if (((uint32_t)r & rm) == rv)
+                            x[r] = neg ? cplx<R>{-x[r].re, -x[r].im} : cmul(x[r], u[3]);
+                }
             }
             break;
         }
