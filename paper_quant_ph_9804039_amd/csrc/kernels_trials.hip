@@ -335,7 +335,7 @@ __device__ __forceinline__ uint32_t trial_index(uint32_t j0, uint32_t w, int r)
 // group qubits (mask rm over the register index, required values rv): an
 // inactive pair takes the identity instead, chosen per pair by a uniform
 // select of the coefficients (form 1 holds the identity), so the register
-// pattern stays fixed.
+// pattern stays fixed; a general complex 2x2 (form 3) skips such pairs.
 template <typename R, int G, int P, int F, bool C>
 __device__ __forceinline__ void trial_pair(const cplx<R> (&u)[4], uint32_t rm, uint32_t rv,
                                            cplx<R> (&x)[1 << G])
@@ -346,7 +346,13 @@ __device__ __forceinline__ void trial_pair(const cplx<R> (&u)[4], uint32_t rm, u
             continue;
         const int r1 = r | (1 << P);
         const cplx<R> a = x[r], b = x[r1];
-        if (C) {
+        if (C && F == 3) {
+            // a complex off-diagonal: skip the pairs that fail the controls
+            if (((uint32_t)r & rm) != rv)
+                continue;
+            x[r] = cmad2(u[0], a, u[1], b);
+            x[r1] = cmad2(u[2], a, u[3], b);
+        } else if (C) {
             const bool on = ((uint32_t)r & rm) == rv;
             const R m00 = on ? u[0].re : R(1), m01 = on ? u[1].re : R(0);
             const R m10 = on ? u[2].re : R(0), m11 = on ? u[3].re : R(1);
@@ -425,7 +431,7 @@ __device__ __forceinline__ void trial_at(uint32_t type, uint32_t form, uint32_t 
     }
     if (rm != 0) {
         if (form == 3)
-            trial_pair<R, G, P, 3, false>(u, 0, 0, x);  // not produced by the gate set
+            trial_pair<R, G, P, 3, true>(u, rm, rv, x);  // no gate of the set lowers to one
         else
             trial_pair<R, G, P, 1, true>(u, rm, rv, x);
         return;
