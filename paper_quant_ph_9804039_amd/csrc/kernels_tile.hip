@@ -330,18 +330,18 @@ __device__ __forceinline__ void group_layout(const TileArgs<R> &A, uint32_t gi, 
     pair0 = e[0] == 1u;
 }
 
-// Fused pass, persistent: each workgroup walks tiles blockIdx.x, +gridDim.x,
-// ...  Each of the T threads holds one quantum of 2^G amplitudes in
-// registers (T * 2^G = 2^k).  While a tile is being worked on, the first
-// group's quanta of the workgroup's next tile are already being loaded, so
-// HBM traffic overlaps the register and LDS work.
 // Waves per SIMD the register budget is sized for.  complex64 with G = 4 is
 // the bench shape: two 512-thread workgroups per CU (LDS allows two 64 KiB
-// tiles) need four waves per SIMD, i.e. at most 128 VGPRs; the compiler
-// otherwise settles just above that and halves the resident workgroups.
+// tiles) need four waves per SIMD, i.e. at most 128 VGPRs.
 template <typename R, int G>
 constexpr int kTileWaves = (sizeof(R) == 4 && G == 4) ? 4 : 1;
 
+// Fused pass, persistent: each workgroup walks tiles blockIdx.x, +gridDim.x,
+// ...  Each of the T threads holds one quantum of 2^G amplitudes in
+// registers (T * 2^G = 2^k).  HBM traffic of one workgroup overlaps the
+// register and LDS work of the other workgroups on the CU (a register
+// prefetch of the next tile measured no faster and costs 2^G amplitudes of
+// registers per thread).
 template <typename R, int G, int T>
 __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kTileWaves<R, G>)))
 k_tile(const TileArgs<R> A)
@@ -369,18 +369,14 @@ k_tile(const TileArgs<R> A)
         o0[i] = spread(e0[i], srun, nsrun);
     const uint64_t rel0 = spread(j00, srun, nsrun);
 
-    cplx<R> x[1 << G], xn[1 << G];
+    cplx<R> x[1 << G];
     uint64_t tile_id = blockIdx.x;
-    if (tile_id < ntiles)
-        load_quantum<R, G>(A.psi + (spread(tile_id, crun, ncrun) | rel0), o0, pair00, x);
 
     for (; tile_id < ntiles; tile_id += gridDim.x) {
         // global index of tile element 0: the tile number spread over the
         // qubits outside the tile, in ascending order
         const uint64_t base = spread(tile_id, crun, ncrun);
-        const uint64_t next = tile_id + gridDim.x;
-        if (next < ntiles)
-            load_quantum<R, G>(A.psi + (spread(next, crun, ncrun) | rel0), o0, pair00, xn);
+        load_quantum<R, G>(A.psi + (base | rel0), o0, pair00, x);
         if (A.scale_in != nullptr) {
             const R sc = (R)*A.scale_in;
 #pragma unroll
@@ -445,9 +441,6 @@ k_tile(const TileArgs<R> A)
             }
             __syncthreads();
         }
-#pragma unroll
-        for (int r = 0; r < (1 << G); ++r)
-            x[r] = xn[r];
     }
 }
 
