@@ -16,7 +16,7 @@ import paper_quant_ph_9804039_amd as q
 pytestmark = pytest.mark.gpu
 
 H_EXACT = float.fromhex("0x1.6a09e667f3bcdp-1")
-MODES = [0, 1]  # fused passes, one pass per gate
+MODES = [0, 1, 2]  # fused passes (reordered), one pass per gate, fused passes in order
 
 
 def state(M, dtype=q.QSIM_C128, **kw):
@@ -85,7 +85,7 @@ def test_permutation_gates_basis_states_bit_exact(mode, dtype):
                         assert np.array_equal(a, want), (M, gate, k)
 
 
-@pytest.mark.parametrize("mode,group", [(0, 3), (0, 4), (0, 5), (1, 0)])
+@pytest.mark.parametrize("mode,group", [(0, 3), (0, 4), (0, 5), (1, 0), (2, 4)])
 @pytest.mark.parametrize("M,kinds", [(15, (cg.X, cg.CNOT, cg.TOFFOLI)),
                                      (15, (cg.X, cg.Z, cg.CNOT, cg.TOFFOLI)),
                                      (10, (cg.Z, cg.X, cg.TOFFOLI))])
