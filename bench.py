@@ -36,8 +36,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-# FP32 vector FMA ceiling without packed-FP32 instructions (which this build
-# never emits): 256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz.
+# FP32 vector FMA ceiling without packed-FP32 instructions (the library's
+# kernels are compiled without them): 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# per FMA x 2.4 GHz.
 # The published 157.3 TFLOP/s counts packed FP32 (two FMAs per lane).
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 M = 30
@@ -203,8 +204,8 @@ def main() -> int:
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
         return 0
     if args.gpus != 1:
-        print("bench.py: this build runs one register on one GPU; --gpus must be 1 "
-              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        print("bench.py: the simulator holds one register on one GPU; --gpus must be 1 "
+              "(sharding a register over several GPUs is not implemented)", file=sys.stderr)
         return 2
 
     import numpy as np
