@@ -337,3 +337,17 @@ def test_invalid_gates_rejected_and_state_untouched():
         with pytest.raises(q.QsimError):
             s.probs(1 << 4)
         assert s.info()["step"] == 1
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dtype,tol_amp,tol_f", [(q.QSIM_C128, 1e-12, 1e-12),
+                                                 (q.QSIM_C64, 2e-5, 1e-6)])
+def test_high_qubit_targets_vs_oracle(mode, dtype, tol_amp, tol_f):
+    """Half of the targets on the top four qubits (the large-register
+    config's shape) at a size the oracle runs in full: the tile set then
+    spans the high qubits, whose amplitudes sit 2^14 and more apart."""
+    M = 18
+    print(f"high-qubit targets mode={mode} dtype={dtype}", flush=True)
+    gates = cg.random_circuit(M, 300, 1018, top_bias=0.5)
+    em = oracle.Errors(sigma=1e-3, p_bitflip=1e-4, p_phaseflip=1e-4, seed=1018, trial=0)
+    _check_vs_oracle(M, gates, dtype, mode, em, tol_amp=tol_amp, tol_f=tol_f)
