@@ -49,7 +49,7 @@ SIGMA = 1e-3
 P_FLIP = 1e-4
 PROBS_MASK = (1 << 10) - 1
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_m30_c64_traffic.json")
-TILE_SOURCE = os.path.join(ROOT, "paper_quant_ph_9804039_amd", "csrc", "kernels_tile.hip")
+TILE_SOURCE = os.path.join(ROOT, "paper_quant_ph_9804039_amd", "csrc", "tile_kernel.h")
 
 
 def log(msg: str) -> None:

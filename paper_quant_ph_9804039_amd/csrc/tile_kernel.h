@@ -19,6 +19,9 @@
 // back; between groups the tile is re-partitioned through LDS.  Threads
 // enumerate the non-group tile bits from the lowest, and the lowest tile bits
 // are the low qubits, so neighbouring lanes touch neighbouring amplitudes.
+#pragma once
+// Included by kernels_tile_c64.hip and kernels_tile_c128.hip, one
+// translation unit per precision so the two compile in parallel.
 #include "launch.h"
 
 namespace qsim {
@@ -53,14 +56,18 @@ __device__ __forceinline__ void st2(cplx<double> *p, cplx<double> a, cplx<double
 // on group bits (mask rc over the register index) are tested, with a uniform
 // test per register; without them every register takes part.  F: the form
 // of a kTPair, 0 = real 2x2 m, 1 = m plus i*w on the diagonal, 2 = the same
-// with m00 = m11 = 0 (a perturbed X).
+// with m00 = m11 = 0 (a perturbed X).  The coefficients are values, so a
+// lane-controlled operation passes per-lane ones (the identity where the
+// lane's controls are not met).
+template <typename R>
+struct PairCoef {
+    R m00, m01, m10, m11, w0, w1;
+};
+
 template <typename R, int G, int P, int F, bool C>
-__device__ __forceinline__ void pair_loop(const TileOp<R> &op, cplx<R> (&x)[1 << G])
+__device__ __forceinline__ void pair_loop(const PairCoef<R> &m, uint32_t rc, cplx<R> (&x)[1 << G])
 {
     // out0 = m00 a + m01 b + i w0 a,  out1 = m10 a + m11 b + i w1 b
-    const R m00 = op.c[0], m01 = op.c[1], m10 = op.c[2], m11 = op.c[3];
-    const R w0 = op.c[4], w1 = op.c[5];
-    const uint32_t rc = C ? op.rc : 0u;
 #pragma unroll
     for (int r = 0; r < (1 << G); ++r) {
         if ((r & (1 << P)) || (C && ((uint32_t)r & rc) != rc))
@@ -69,16 +76,16 @@ __device__ __forceinline__ void pair_loop(const TileOp<R> &op, cplx<R> (&x)[1 <<
         const cplx<R> a = x[r], b = x[r1];
         cplx<R> na, nb;
         if (F == 2) {
-            na = {m01 * b.re - w0 * a.im, m01 * b.im + w0 * a.re};
-            nb = {m10 * a.re - w1 * b.im, m10 * a.im + w1 * b.re};
+            na = {m.m01 * b.re - m.w0 * a.im, m.m01 * b.im + m.w0 * a.re};
+            nb = {m.m10 * a.re - m.w1 * b.im, m.m10 * a.im + m.w1 * b.re};
         } else {
-            na = {m00 * a.re + m01 * b.re, m00 * a.im + m01 * b.im};
-            nb = {m10 * a.re + m11 * b.re, m10 * a.im + m11 * b.im};
+            na = {m.m00 * a.re + m.m01 * b.re, m.m00 * a.im + m.m01 * b.im};
+            nb = {m.m10 * a.re + m.m11 * b.re, m.m10 * a.im + m.m11 * b.im};
             if (F == 1) {
-                na.re -= w0 * a.im;
-                na.im += w0 * a.re;
-                nb.re -= w1 * b.im;
-                nb.im += w1 * b.re;
+                na.re -= m.w0 * a.im;
+                na.im += m.w0 * a.re;
+                nb.re -= m.w1 * b.im;
+                nb.im += m.w1 * b.re;
             }
         }
         x[r] = na;
@@ -86,26 +93,24 @@ __device__ __forceinline__ void pair_loop(const TileOp<R> &op, cplx<R> (&x)[1 <<
     }
 }
 
-template <typename R, int G, int P, bool C>
-__device__ __forceinline__ void swap_loop(const TileOp<R> &op, cplx<R> (&x)[1 << G])
+// L: lane-controlled, the pair is exchanged only where `act` holds.
+template <typename R, int G, int P, bool C, bool L>
+__device__ __forceinline__ void swap_loop(uint32_t rc, bool act, cplx<R> (&x)[1 << G])
 {
-    const uint32_t rc = C ? op.rc : 0u;
 #pragma unroll
     for (int r = 0; r < (1 << G); ++r) {
         if ((r & (1 << P)) || (C && ((uint32_t)r & rc) != rc))
             continue;
         const int r1 = r | (1 << P);
-        const cplx<R> a = x[r];
-        x[r] = x[r1];
-        x[r1] = a;
+        const cplx<R> a = x[r], b = x[r1];
+        x[r] = (!L || act) ? b : a;
+        x[r1] = (!L || act) ? a : b;
     }
 }
 
 template <typename R, int G, int P, bool C>
-__device__ __forceinline__ void diag_loop(const TileOp<R> &op, cplx<R> (&x)[1 << G])
+__device__ __forceinline__ void diag_loop(cplx<R> d0, cplx<R> d1, uint32_t rc, cplx<R> (&x)[1 << G])
 {
-    const cplx<R> d0 = {op.c[0], op.c[1]}, d1 = {op.c[2], op.c[3]};
-    const uint32_t rc = C ? op.rc : 0u;
 #pragma unroll
     for (int r = 0; r < (1 << G); ++r) {
         if (C && ((uint32_t)r & rc) != rc)
@@ -125,21 +130,27 @@ __device__ __forceinline__ void phase_loop(const TileOp<R> &op, cplx<R> (&x)[1 <
             x[r] = cmul(x[r], q);
 }
 
-template <typename R, int G, int P, bool C>
-__device__ __forceinline__ void neg_loop(const TileOp<R> &op, cplx<R> (&x)[1 << G])
+template <typename R, int G, int P, bool C, bool L>
+__device__ __forceinline__ void neg_loop(uint32_t rc, bool act, cplx<R> (&x)[1 << G])
 {
-    const uint32_t rc = C ? op.rc : 0u;
 #pragma unroll
     for (int r = 0; r < (1 << G); ++r) {
         if (!((r >> P) & 1) || (C && ((uint32_t)r & rc) != rc))
             continue;
-        x[r] = {-x[r].re, -x[r].im};
+        const cplx<R> n = {-x[r].re, -x[r].im};
+        x[r] = (!L || act) ? n : x[r];
     }
 }
 
-// One operation on the registers of group bit P.  Operations without a
-// control on a group bit (the common case) take loops with no per-register
-// tests.
+template <typename R>
+__device__ __forceinline__ PairCoef<R> pair_coef(const TileOp<R> &op)
+{
+    return {op.c[0], op.c[1], op.c[2], op.c[3], op.c[4], op.c[5]};
+}
+
+// One operation on the registers of group bit P, for every lane of the
+// quantum.  Operations without a control on a group bit (the common case)
+// take loops with no per-register tests.
 template <typename R, int G, int P>
 __device__ __forceinline__ void apply_at(const TileOp<R> &op, cplx<R> (&x)[1 << G])
 {
@@ -147,75 +158,118 @@ __device__ __forceinline__ void apply_at(const TileOp<R> &op, cplx<R> (&x)[1 << 
     switch (op.kind) {
     case kTPair:
         if (ctl)
-            pair_loop<R, G, P, 1, true>(op, x);
+            pair_loop<R, G, P, 1, true>(pair_coef(op), op.rc, x);
         else if (op.form == 0)
-            pair_loop<R, G, P, 0, false>(op, x);
+            pair_loop<R, G, P, 0, false>(pair_coef(op), 0u, x);
         else if (op.form == 1)
-            pair_loop<R, G, P, 1, false>(op, x);
+            pair_loop<R, G, P, 1, false>(pair_coef(op), 0u, x);
         else
-            pair_loop<R, G, P, 2, false>(op, x);
+            pair_loop<R, G, P, 2, false>(pair_coef(op), 0u, x);
         break;
     case kTSwap:
         if (ctl)
-            swap_loop<R, G, P, true>(op, x);
+            swap_loop<R, G, P, true, false>(op.rc, true, x);
         else
-            swap_loop<R, G, P, false>(op, x);
+            swap_loop<R, G, P, false, false>(0u, true, x);
         break;
     case kTPhaseIn:  // never controlled
         phase_loop<R, G, P>(op, x);
         break;
-    case kTDiagIn:
+    case kTDiagIn: {
+        const cplx<R> d0 = {op.c[0], op.c[1]}, d1 = {op.c[2], op.c[3]};
         if (ctl)
-            diag_loop<R, G, P, true>(op, x);
+            diag_loop<R, G, P, true>(d0, d1, op.rc, x);
         else
-            diag_loop<R, G, P, false>(op, x);
+            diag_loop<R, G, P, false>(d0, d1, 0u, x);
         break;
+    }
     default:  // kTNegIn
         if (ctl)
-            neg_loop<R, G, P, true>(op, x);
+            neg_loop<R, G, P, true, false>(op.rc, true, x);
         else
-            neg_loop<R, G, P, false>(op, x);
+            neg_loop<R, G, P, false, false>(0u, true, x);
         break;
     }
 }
 
-// Apply the operations [first, first + cnt) of a group to one quantum.
-// An uncontrolled diagonal reaches the kernel as diag(1, q), its d0 having
-// been moved into the pass's global phase (a scalar commutes with
-// everything).  On a bit outside the group it commutes with everything else
-// in the group (those act on group bits only), and its factor is the same
-// for all registers of the quantum: such factors are multiplied into one
-// factor F, applied once at the end; the last group's F starts from the
-// global phase.
-template <typename R, int G>
-__device__ __forceinline__ void apply_group(const TileArgs<R> &A, uint32_t first, uint32_t cnt,
-                                            cplx<R> (&x)[1 << G], uint32_t j0, uint64_t base,
-                                            bool last)
+// The same for an operation with controls on lane (non-group tile) bits:
+// `act` says whether this lane's controls are met.  The lanes of a wave
+// differ here, so instead of branching per lane (which would make the
+// compiler copy the whole quantum around every operation to keep the
+// inactive lanes' values), the operation is applied everywhere with
+// per-lane coefficients that are the identity where act is false.
+template <typename R, int G, int P>
+__device__ __forceinline__ void apply_at_lane(const TileOp<R> &op, bool act, cplx<R> (&x)[1 << G])
 {
-    static_assert(G >= 3 && G <= 5, "group bits");
-    // the last group also carries the pass's global phase
-    const bool ph = last && A.use_phase != 0;
-    cplx<R> F = ph ? cplx<R>{A.phase[0], A.phase[1]} : cplx<R>{R(1), R(0)};
-    bool useF = ph;
-    for (uint32_t o = first; o < first + cnt; ++o) {
-        const TileOp<R> op = A.ops[o];  // whole descriptor at once: one scalar wait
-        if ((base & op.cm_out) != op.cm_out || (j0 & op.qc) != op.qc)
-            continue;
-        if (op.kind >= kTDiagOut) {
-            const uint32_t bit = op.tpos != kNoPos ? ((j0 >> op.tpos) & 1u)
-                                                  : (uint32_t)((base >> op.tq) & 1u);
-            if (op.kind == kTNegOut) {
-                if (bit) {
-                    F = {-F.re, -F.im};
-                    useF = true;
-                }
-            } else {
-                const cplx<R> d = bit ? cplx<R>{op.c[2], op.c[3]} : cplx<R>{op.c[0], op.c[1]};
-                F = cmul(F, d);
-                useF = true;
-            }
-            continue;
+    const bool ctl = op.rc != 0;
+    const R one = R(1), zero = R(0);
+    switch (op.kind) {
+    case kTPair: {
+        const PairCoef<R> m = {act ? op.c[0] : one, act ? op.c[1] : zero, act ? op.c[2] : zero,
+                               act ? op.c[3] : one, act ? op.c[4] : zero, act ? op.c[5] : zero};
+        if (ctl)
+            pair_loop<R, G, P, 1, true>(m, op.rc, x);
+        else if (op.form == 0)
+            pair_loop<R, G, P, 0, false>(m, 0u, x);
+        else
+            pair_loop<R, G, P, 1, false>(m, 0u, x);
+        break;
+    }
+    case kTSwap:
+        if (ctl)
+            swap_loop<R, G, P, true, true>(op.rc, act, x);
+        else
+            swap_loop<R, G, P, false, true>(0u, act, x);
+        break;
+    case kTDiagIn: {
+        const cplx<R> d0 = {act ? op.c[0] : one, act ? op.c[1] : zero};
+        const cplx<R> d1 = {act ? op.c[2] : one, act ? op.c[3] : zero};
+        if (ctl)
+            diag_loop<R, G, P, true>(d0, d1, op.rc, x);
+        else
+            diag_loop<R, G, P, false>(d0, d1, 0u, x);
+        break;
+    }
+    default:  // kTNegIn (kTPhaseIn is never controlled)
+        if (ctl)
+            neg_loop<R, G, P, true, true>(op.rc, act, x);
+        else
+            neg_loop<R, G, P, false, true>(0u, act, x);
+        break;
+    }
+}
+
+// One operation of a group on one quantum.  An uncontrolled diagonal
+// reaches the kernel as diag(1, q), its d0 having been moved into the pass's
+// global phase (a scalar commutes with everything).  On a bit outside the
+// group it commutes with everything else in the group (those act on group
+// bits only), and its factor is the same for all registers of the quantum:
+// such factors are multiplied into one factor F, applied once at the end of
+// the group.  Every branch here is uniform over the wave: the controls
+// outside the tile are constants of the tile, and those on lane bits are
+// applied through per-lane coefficients.
+template <typename R, int G>
+__device__ __forceinline__ void apply_op(const TileOp<R> &op, cplx<R> (&x)[1 << G], uint32_t j0,
+                                         uint64_t base, cplx<R> &F, bool &useF)
+{
+    if ((base & op.cm_out) != op.cm_out)
+        return;
+    if (op.kind >= kTDiagOut) {
+        // never controlled; the factor depends on the lane where the target
+        // is a lane bit
+        const bool bit = op.tpos != kNoPos ? ((j0 >> op.tpos) & 1u) != 0
+                                           : ((base >> op.tq) & 1u) != 0;
+        if (op.kind == kTNegOut) {
+            const cplx<R> n = {-F.re, -F.im};
+            F = bit ? n : F;
+        } else {
+            const cplx<R> d = bit ? cplx<R>{op.c[2], op.c[3]} : cplx<R>{op.c[0], op.c[1]};
+            F = cmul(F, d);
         }
+        useF = true;
+        return;
+    }
+    if (op.qc == 0) {
         switch (op.gpos) {
         case 0: apply_at<R, G, 0>(op, x); break;
         case 1: apply_at<R, G, 1>(op, x); break;
@@ -223,6 +277,32 @@ __device__ __forceinline__ void apply_group(const TileArgs<R> &A, uint32_t first
         case 3: if constexpr (G > 3) apply_at<R, G, 3>(op, x); break;
         default: if constexpr (G > 4) apply_at<R, G, 4>(op, x); break;
         }
+    } else {
+        const bool act = (j0 & op.qc) == op.qc;
+        switch (op.gpos) {
+        case 0: apply_at_lane<R, G, 0>(op, act, x); break;
+        case 1: apply_at_lane<R, G, 1>(op, act, x); break;
+        case 2: apply_at_lane<R, G, 2>(op, act, x); break;
+        case 3: if constexpr (G > 3) apply_at_lane<R, G, 3>(op, act, x); break;
+        default: if constexpr (G > 4) apply_at_lane<R, G, 4>(op, act, x); break;
+        }
+    }
+}
+
+// Apply the operations [first, first + cnt) of a group to one quantum; the
+// last group's F starts from the pass's global phase.
+template <typename R, int G>
+__device__ __forceinline__ void apply_group(const TileArgs<R> &A, uint32_t first, uint32_t cnt,
+                                            cplx<R> (&x)[1 << G], uint32_t j0, uint64_t base,
+                                            bool last)
+{
+    static_assert(G >= 3 && G <= 5, "group bits");
+    const bool ph = last && A.use_phase != 0;
+    cplx<R> F = ph ? cplx<R>{A.phase[0], A.phase[1]} : cplx<R>{R(1), R(0)};
+    bool useF = ph;
+    for (uint32_t o = first; o < first + cnt; ++o) {
+        const TileOp<R> op = A.ops[o];  // whole descriptor at once: one scalar wait
+        apply_op<R, G>(op, x, j0, base, F, useF);
     }
     if (useF) {
 #pragma unroll
@@ -501,11 +581,6 @@ hipError_t launch_g(const TileArgs<R> &A, hipStream_t st)
 
 }  // namespace
 
-size_t tile_lds_bytes(int k, int elem_bytes)
-{
-    return ((size_t)1 << k) * (size_t)elem_bytes;
-}
-
 template <typename R>
 hipError_t launch_tile(const TileArgs<R> &A, int G, hipStream_t st)
 {
@@ -516,8 +591,5 @@ hipError_t launch_tile(const TileArgs<R> &A, int G, hipStream_t st)
     default: return hipErrorInvalidValue;
     }
 }
-
-template hipError_t launch_tile<float>(const TileArgs<float> &, int, hipStream_t);
-template hipError_t launch_tile<double>(const TileArgs<double> &, int, hipStream_t);
 
 }  // namespace qsim
