@@ -41,9 +41,19 @@ def sources():
                   if f.endswith((".hip", ".cpp")))
 
 
+# The fused tile pass dispatches on its uniform operation stream: leaving
+# uniform branch regions unstructurized keeps the register quantum in place
+# across the dispatch instead of copying it through the structurizer's flow
+# blocks.
+FILE_FLAGS = {
+    "kernels_tile_c64.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"],
+    "kernels_tile_c128.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"],
+}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
-    cmd = [hipcc()] + HIP_FLAGS + ["-c", src, "-o", obj]
+    cmd = [hipcc()] + HIP_FLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(ln for ln in (r.stdout + r.stderr).splitlines()
                      if "packed-fp32-ops" not in ln)
