@@ -103,8 +103,11 @@ __device__ __forceinline__ void swap_loop(uint32_t rc, bool act, cplx<R> (&x)[1 
             continue;
         const int r1 = r | (1 << P);
         const cplx<R> a = x[r], b = x[r1];
-        x[r] = (!L || act) ? b : a;
-        x[r1] = (!L || act) ? a : b;
+        // selects on the components: a select of whole structs can become a
+        // select of their addresses, which keeps the quantum out of registers
+        const bool s = !L || act;
+        x[r] = {s ? b.re : a.re, s ? b.im : a.im};
+        x[r1] = {s ? a.re : b.re, s ? a.im : b.im};
     }
 }
 
@@ -137,8 +140,8 @@ __device__ __forceinline__ void neg_loop(uint32_t rc, bool act, cplx<R> (&x)[1 <
     for (int r = 0; r < (1 << G); ++r) {
         if (!((r >> P) & 1) || (C && ((uint32_t)r & rc) != rc))
             continue;
-        const cplx<R> n = {-x[r].re, -x[r].im};
-        x[r] = (!L || act) ? n : x[r];
+        const bool s = !L || act;
+        x[r] = {s ? -x[r].re : x[r].re, s ? -x[r].im : x[r].im};
     }
 }
 
@@ -260,10 +263,9 @@ __device__ __forceinline__ void apply_op(const TileOp<R> &op, cplx<R> (&x)[1 << 
         const bool bit = op.tpos != kNoPos ? ((j0 >> op.tpos) & 1u) != 0
                                            : ((base >> op.tq) & 1u) != 0;
         if (op.kind == kTNegOut) {
-            const cplx<R> n = {-F.re, -F.im};
-            F = bit ? n : F;
+            F = {bit ? -F.re : F.re, bit ? -F.im : F.im};
         } else {
-            const cplx<R> d = bit ? cplx<R>{op.c[2], op.c[3]} : cplx<R>{op.c[0], op.c[1]};
+            const cplx<R> d = {bit ? op.c[2] : op.c[0], bit ? op.c[3] : op.c[1]};
             F = cmul(F, d);
         }
         useF = true;
