@@ -292,7 +292,10 @@ __device__ __forceinline__ void apply_op(const TileOp<R> &op, cplx<R> (&x)[1 << 
 }
 
 // Apply the operations [first, first + cnt) of a group to one quantum; the
-// last group's F starts from the pass's global phase.
+// last group's F starts from the pass's global phase.  An operation's
+// results land in other registers than its inputs; with two operations per
+// trip of the loop the second writes them back where the first read them,
+// so no copy of the quantum closes each trip.
 template <typename R, int G>
 __device__ __forceinline__ void apply_group(const TileArgs<R> &A, uint32_t first, uint32_t cnt,
                                             cplx<R> (&x)[1 << G], uint32_t j0, uint64_t base,
@@ -302,9 +305,14 @@ __device__ __forceinline__ void apply_group(const TileArgs<R> &A, uint32_t first
     const bool ph = last && A.use_phase != 0;
     cplx<R> F = ph ? cplx<R>{A.phase[0], A.phase[1]} : cplx<R>{R(1), R(0)};
     bool useF = ph;
-    for (uint32_t o = first; o < first + cnt; ++o) {
+    const uint32_t end = first + cnt;
+    for (uint32_t o = first; o < end; o += 2) {
         const TileOp<R> op = A.ops[o];  // whole descriptor at once: one scalar wait
         apply_op<R, G>(op, x, j0, base, F, useF);
+        if (o + 1 >= end)
+            break;
+        const TileOp<R> op2 = A.ops[o + 1];
+        apply_op<R, G>(op2, x, j0, base, F, useF);
     }
     if (useF) {
 #pragma unroll
