@@ -41,13 +41,15 @@ def sources():
                   if f.endswith((".hip", ".cpp")))
 
 
-# The fused tile pass dispatches on its uniform operation stream: leaving
+# The fused tile pass and the Monte Carlo register-group kernel dispatch on
+# a uniform operation stream: leaving
 # uniform branch regions unstructurized keeps the register quantum in place
 # across the dispatch instead of copying it through the structurizer's flow
 # blocks.
 FILE_FLAGS = {
     "kernels_tile_c64.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"],
     "kernels_tile_c128.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"],
+    "kernels_trials.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"],
 }
 
 

@@ -377,27 +377,32 @@ __device__ __forceinline__ void trial_pair(const cplx<R> (&u)[4], uint32_t rm, u
     }
 }
 
-template <typename R, int G, int P, bool C>
-__device__ __forceinline__ void trial_swap(uint32_t rm, uint32_t rv, cplx<R> (&x)[1 << G])
+// L: controls on lane qubits; the pair is exchanged only where `act` holds.
+template <typename R, int G, int P, bool C, bool L>
+__device__ __forceinline__ void trial_swap(uint32_t rm, uint32_t rv, bool act, cplx<R> (&x)[1 << G])
 {
 #pragma unroll
     for (int r = 0; r < (1 << G); ++r) {
         if ((r & (1 << P)) || (C && ((uint32_t)r & rm) != rv))
             continue;
         const int r1 = r | (1 << P);
-        const cplx<R> a = x[r];
-        x[r] = x[r1];
-        x[r1] = a;
+        const cplx<R> a = x[r], b = x[r1];
+        // selects on the components (a select of whole structs can become a
+        // select of addresses, which keeps the quantum out of registers)
+        const bool s = !L || act;
+        x[r] = {s ? b.re : a.re, s ? b.im : a.im};
+        x[r1] = {s ? a.re : b.re, s ? a.im : b.im};
     }
 }
 
 // diag(1, q) or a sign flip on group position P (registers whose bit P is
-// `on`), under controls on group qubits.
+// `on`), under controls on group qubits.  A lane-controlled caller passes
+// q = 1 where its controls are not met, and a sign flip as q = -1.
 template <typename R, int G, int P>
 __device__ __forceinline__ void trial_phase(bool neg, uint32_t on, cplx<R> q, uint32_t rm,
                                             uint32_t rv, cplx<R> (&x)[1 << G])
 {
-    if (!neg && rm == 0) {
+    if (!neg && rm == 0 && on == 1u) {
         // an uncontrolled phase (Rz): half of the registers move
 #pragma unroll
         for (int r = 0; r < (1 << G); ++r)
@@ -405,28 +410,63 @@ __device__ __forceinline__ void trial_phase(bool neg, uint32_t on, cplx<R> q, ui
                 x[r] = cmul(x[r], q);
         return;
     }
+    if (neg) {
 #pragma unroll
-    for (int r = 0; r < (1 << G); ++r) {
-        if ((((uint32_t)r >> P) & 1u) != on || ((uint32_t)r & rm) != rv)
-            continue;
-        x[r] = neg ? cplx<R>{-x[r].re, -x[r].im} : cmul(x[r], q);
+        for (int r = 0; r < (1 << G); ++r)
+            if ((((uint32_t)r >> P) & 1u) == on && ((uint32_t)r & rm) == rv)
+                x[r] = {-x[r].re, -x[r].im};
+        return;
     }
+#pragma unroll
+    for (int r = 0; r < (1 << G); ++r)
+        if ((((uint32_t)r >> P) & 1u) == on && ((uint32_t)r & rm) == rv)
+            x[r] = cmul(x[r], q);
 }
 
-template <typename R, int G, int P>
+// One gate with its target on group position P.  L: the gate has controls
+// on lane qubits, met where `act` holds; it then runs on every lane with
+// coefficients that are the identity where they are not met, so every
+// branch here is uniform over the wave.
+template <typename R, int G, int P, bool L>
 __device__ __forceinline__ void trial_at(uint32_t type, uint32_t form, uint32_t neg_val,
                                          const cplx<R> (&u)[4], uint32_t rm, uint32_t rv,
-                                         cplx<R> (&x)[1 << G])
+                                         bool act, cplx<R> (&x)[1 << G])
 {
     if (type == kOpSwap) {
         if (rm == 0)
-            trial_swap<R, G, P, false>(rm, rv, x);
+            trial_swap<R, G, P, false, L>(rm, rv, act, x);
         else
-            trial_swap<R, G, P, true>(rm, rv, x);
+            trial_swap<R, G, P, true, L>(rm, rv, act, x);
         return;
     }
     if (type == kOpDiag || type == kOpNeg) {
-        trial_phase<R, G, P>(type == kOpNeg, type == kOpNeg ? neg_val : 1u, u[3], rm, rv, x);
+        const bool neg = type == kOpNeg;
+        const uint32_t on = neg ? neg_val : 1u;
+        if (!L) {
+            trial_phase<R, G, P>(neg, on, u[3], rm, rv, x);
+        } else {
+            const cplx<R> f = neg ? cplx<R>{R(-1), R(0)} : u[3];
+            const cplx<R> q = {act ? f.re : R(1), act ? f.im : R(0)};
+            trial_phase<R, G, P>(false, on, q, rm, rv, x);
+        }
+        return;
+    }
+    if (L) {
+        const cplx<R> v[4] = {{act ? u[0].re : R(1), act ? u[0].im : R(0)},
+                              {act ? u[1].re : R(0), act ? u[1].im : R(0)},
+                              {act ? u[2].re : R(0), act ? u[2].im : R(0)},
+                              {act ? u[3].re : R(1), act ? u[3].im : R(0)}};
+        if (form == 3) {
+            if (rm != 0)
+                trial_pair<R, G, P, 3, true>(v, rm, rv, x);
+            else
+                trial_pair<R, G, P, 3, false>(v, rm, rv, x);
+        } else {
+            if (rm != 0)
+                trial_pair<R, G, P, 1, true>(v, rm, rv, x);
+            else
+                trial_pair<R, G, P, 1, false>(v, rm, rv, x);
+        }
         return;
     }
     if (rm != 0) {
@@ -444,55 +484,76 @@ __device__ __forceinline__ void trial_at(uint32_t type, uint32_t form, uint32_t 
     }
 }
 
+template <typename R, int G, bool L>
+__device__ __forceinline__ void trial_dispatch(uint32_t P, uint32_t type, uint32_t form,
+                                               uint32_t neg_val, const cplx<R> (&u)[4],
+                                               uint32_t rm, uint32_t rv, bool act,
+                                               cplx<R> (&x)[1 << G])
+{
+    switch (P) {
+    case 0: trial_at<R, G, 0, L>(type, form, neg_val, u, rm, rv, act, x); break;
+    case 1: trial_at<R, G, 1, L>(type, form, neg_val, u, rm, rv, act, x); break;
+    case 2: trial_at<R, G, 2, L>(type, form, neg_val, u, rm, rv, act, x); break;
+    case 3: if constexpr (G > 3) trial_at<R, G, 3, L>(type, form, neg_val, u, rm, rv, act, x); break;
+    default: if constexpr (G > 4) trial_at<R, G, 4, L>(type, form, neg_val, u, rm, rv, act, x); break;
+    }
+}
+
 // One trial operation on the thread's registers (base index j0).  The
-// record's fields are uniform and read with scalar loads.
+// record's fields are uniform and read with scalar loads, and every branch
+// is uniform over the wave.  A diagonal or sign flip on a qubit outside the
+// group, and the phase flips on lane qubits after a gate, are diagonal in
+// the lane qubits: they commute with the group's other gates (whose targets
+// are group qubits) and multiply the whole quantum by a per-lane factor,
+// collected in F and applied once at the end of the group (useF).
 template <typename R, int G>
 __device__ __forceinline__ void trial_apply(const TrialGateOp<R> &op, uint32_t j0,
-                                            cplx<R> (&x)[1 << G])
+                                            cplx<R> (&x)[1 << G], cplx<R> &F, bool &useF)
 {
     const uint32_t meta = op.meta, regs = op.regs;
     const uint32_t type = meta & 15u, form = (meta >> 4) & 15u, neg_val = (meta >> 8) & 1u;
     const uint32_t P = (meta >> 12) & 15u;
     const uint32_t rm = regs & 255u, rv = (regs >> 8) & 255u, rz = (regs >> 16) & 255u;
     const uint32_t zmask = op.zmask;
-    if ((j0 & op.lm) == op.lv) {
-        cplx<R> u[4];
+    const bool act = (j0 & op.lm) == op.lv;
+    cplx<R> u[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            u[k] = op.u[k];
-        switch (P) {
-        case 0: trial_at<R, G, 0>(type, form, neg_val, u, rm, rv, x); break;
-        case 1: trial_at<R, G, 1>(type, form, neg_val, u, rm, rv, x); break;
-        case 2: trial_at<R, G, 2>(type, form, neg_val, u, rm, rv, x); break;
-        case 3: if constexpr (G > 3) trial_at<R, G, 3>(type, form, neg_val, u, rm, rv, x); break;
-        case 4: if constexpr (G > 4) trial_at<R, G, 4>(type, form, neg_val, u, rm, rv, x); break;
-        default: {
-            // a diagonal or sign flip on a qubit that is not a group qubit:
-            // the thread's bit of it decides, for all of its registers
-            const uint32_t target = (meta >> 16) & 31u;
-            const bool neg = type == kOpNeg;
-            if (((j0 >> target) & 1u) == (neg ? neg_val : 1u)) {
-                if (!neg && rm == 0) {
+    for (int k = 0; k < 4; ++k)
+        u[k] = op.u[k];
+    if (P < (uint32_t)G) {
+        if (op.lm == 0)
+            trial_dispatch<R, G, false>(P, type, form, neg_val, u, rm, rv, true, x);
+        else
+            trial_dispatch<R, G, true>(P, type, form, neg_val, u, rm, rv, act, x);
+    } else {
+        // the thread's bit of the target decides, for all of its registers
+        const uint32_t target = (meta >> 16) & 31u;
+        const bool neg = type == kOpNeg;
+        const bool hit = act && ((j0 >> target) & 1u) == (neg ? neg_val : 1u);
+        const cplx<R> f = neg ? cplx<R>{R(-1), R(0)} : u[3];
+        const cplx<R> q = {hit ? f.re : R(1), hit ? f.im : R(0)};
+        if (rm == 0) {
+            F = cmul(F, q);
+            useF = true;
+        } else {
 #pragma unroll
-                    for (int r = 0; r < (1 << G); ++r)
-                        x[r] = cmul(x[r], u[3]);
-                } else {
-#pragma unroll
-                    for (int r = 0; r < (1 << G); ++r)
-                        if (((uint32_t)r & rm) == rv)
-                            x[r] = neg ? cplx<R>{-x[r].re, -x[r].im} : cmul(x[r], u[3]);
-                }
-            }
-            break;
-        }
+            for (int r = 0; r < (1 << G); ++r)
+                if (((uint32_t)r & rm) == rv)
+                    x[r] = cmul(x[r], q);
         }
     }
     if ((zmask | rz) != 0) {
-        const uint32_t lpar = __popc(j0 & zmask) & 1u;
+        const bool lpar = (__popc(j0 & zmask) & 1u) != 0;
+        if (rz == 0) {
+            F = {lpar ? -F.re : F.re, lpar ? -F.im : F.im};
+            useF = true;
+        } else {
 #pragma unroll
-        for (int r = 0; r < (1 << G); ++r)
-            if ((lpar ^ (__popc((uint32_t)r & rz) & 1u)) != 0)
-                x[r] = {-x[r].re, -x[r].im};
+            for (int r = 0; r < (1 << G); ++r) {
+                const bool s = lpar != ((__popc((uint32_t)r & rz) & 1u) != 0);
+                x[r] = {s ? -x[r].re : x[r].re, s ? -x[r].im : x[r].im};
+            }
+        }
     }
 }
 
@@ -664,8 +725,22 @@ __global__ void __launch_bounds__(T) k_trials_groups(const TrialLaunch L, uint64
                     x[r] = buf[trial_slot<R>(trial_index<G>(j0, w, r))];
                 __syncthreads();
             }
-            for (uint32_t g = first; g < first + count; ++g)
-                trial_apply<R, G>(tops[g], j0, x);
+            // two gates per trip: a gate's results land in other registers
+            // than its inputs, and the second writes them back
+            cplx<R> F = {R(1), R(0)};
+            bool useF = false;
+            const uint32_t end = first + count;
+            for (uint32_t g = first; g < end; g += 2) {
+                trial_apply<R, G>(tops[g], j0, x, F, useF);
+                if (g + 1 >= end)
+                    break;
+                trial_apply<R, G>(tops[g + 1], j0, x, F, useF);
+            }
+            if (useF) {
+#pragma unroll
+                for (int r = 0; r < (1 << G); ++r)
+                    x[r] = cmul(x[r], F);
+            }
         }
         // fidelity against the error-free register, reading psi(i) = s(i ^ X)
         const uint32_t X = Xs[b];
