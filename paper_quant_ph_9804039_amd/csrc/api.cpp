@@ -727,6 +727,19 @@ void build_tile_args(const qsim_state *s, const std::vector<Op> &ops, const Pass
                 // real off-diagonal (fusable() admits no other matrix): real
                 // 2x2 plus i*w on the diagonal
                 t.kind = kTPair;
+                if (op.cmask == 0 && u[0] != 0.0 && u[2] == u[0] && u[4] == u[0] &&
+                    u[6] == -u[0] && u[7] == u[1]) {
+                    // h [[1, 1], [1, -1]] + i w (a Hadamard, perturbed or
+                    // not) = h ([[1, 1], [1, -1]] + i w/h): the real scalar h
+                    // joins the pass's global phase and the pair becomes a
+                    // butterfly, a +- b plus i (w/h) on the diagonal
+                    const double h = u[0], tw = u[1] / h;
+                    phase_re *= h;
+                    phase_im *= h;
+                    t.c[4] = (R)tw; t.c[5] = (R)tw;
+                    t.form = tw != 0.0 ? 3 : 4;
+                    break;
+                }
                 t.c[0] = (R)u[0]; t.c[1] = (R)u[2]; t.c[2] = (R)u[4]; t.c[3] = (R)u[6];
                 t.c[4] = (R)u[1]; t.c[5] = (R)u[7];
                 t.form = (u[1] != 0.0 || u[7] != 0.0) ? (u[0] == 0.0 && u[6] == 0.0 ? 2 : 1) : 0;

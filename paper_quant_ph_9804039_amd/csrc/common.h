@@ -146,7 +146,9 @@ struct TileOp {
     uint8_t kind;       // TileOpKind
     uint8_t gpos;       // target's index among the group bits (kinds 0..4)
     uint8_t rc;         // controls on group bits, as a mask over the register index
-    uint8_t form;       // kTPair: 0 real m; 1 m + i*w on the diagonal; 2 the same, m00 = m11 = 0
+    uint8_t form;       // kTPair: 0 real m; 1 m + i*w on the diagonal; 2 the same, m00 = m11 = 0;
+                        // 3 (never controlled) h*([[1,1],[1,-1]] + i*t) with h in the pass phase,
+                        // t = c[4]; 4 the same with t = 0
     uint32_t qc;        // controls on tile bits outside the group, as a tile-index mask
     uint64_t cm_out;    // controls on qubits outside the tile, as a global mask
     uint32_t tpos;      // kinds 5, 6: tile bit of the target, kNoPos if outside the tile

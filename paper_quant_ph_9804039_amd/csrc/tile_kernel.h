@@ -56,9 +56,11 @@ __device__ __forceinline__ void st2(cplx<double> *p, cplx<double> a, cplx<double
 // on group bits (mask rc over the register index) are tested, with a uniform
 // test per register; without them every register takes part.  F: the form
 // of a kTPair, 0 = real 2x2 m, 1 = m plus i*w on the diagonal, 2 = the same
-// with m00 = m11 = 0 (a perturbed X).  The coefficients are values, so a
-// lane-controlled operation passes per-lane ones (the identity where the
-// lane's controls are not met).
+// with m00 = m11 = 0 (a perturbed X), 3 = the butterfly a + b, a - b plus
+// i*w on the diagonal (a Hadamard whose scale h joined the pass's phase), 4 =
+// the same with w = 0.  The coefficients are values, so a lane-controlled
+// operation passes per-lane ones (the identity where the lane's controls are
+// not met).
 template <typename R>
 struct PairCoef {
     R m00, m01, m10, m11, w0, w1;
@@ -75,7 +77,13 @@ __device__ __forceinline__ void pair_loop(const PairCoef<R> &m, uint32_t rc, cpl
         const int r1 = r | (1 << P);
         const cplx<R> a = x[r], b = x[r1];
         cplx<R> na, nb;
-        if (F == 2) {
+        if (F == 4) {
+            na = {a.re + b.re, a.im + b.im};
+            nb = {a.re - b.re, a.im - b.im};
+        } else if (F == 3) {
+            na = {(a.re + b.re) - m.w0 * a.im, (a.im + b.im) + m.w0 * a.re};
+            nb = {(a.re - b.re) - m.w0 * b.im, (a.im - b.im) + m.w0 * b.re};
+        } else if (F == 2) {
             na = {m.m01 * b.re - m.w0 * a.im, m.m01 * b.im + m.w0 * a.re};
             nb = {m.m10 * a.re - m.w1 * b.im, m.m10 * a.im + m.w1 * b.re};
         } else {
@@ -166,8 +174,12 @@ __device__ __forceinline__ void apply_at(const TileOp<R> &op, cplx<R> (&x)[1 << 
             pair_loop<R, G, P, 0, false>(pair_coef(op), 0u, x);
         else if (op.form == 1)
             pair_loop<R, G, P, 1, false>(pair_coef(op), 0u, x);
-        else
+        else if (op.form == 2)
             pair_loop<R, G, P, 2, false>(pair_coef(op), 0u, x);
+        else if (op.form == 3)
+            pair_loop<R, G, P, 3, false>(pair_coef(op), 0u, x);
+        else
+            pair_loop<R, G, P, 4, false>(pair_coef(op), 0u, x);
         break;
     case kTSwap:
         if (ctl)
