@@ -81,8 +81,10 @@ __device__ __forceinline__ void pair_loop(const PairCoef<R> &m, uint32_t rc, cpl
             na = {a.re + b.re, a.im + b.im};
             nb = {a.re - b.re, a.im - b.im};
         } else if (F == 3) {
-            na = {(a.re + b.re) - m.w0 * a.im, (a.im + b.im) + m.w0 * a.re};
-            nb = {(a.re - b.re) - m.w0 * b.im, (a.im - b.im) + m.w0 * b.re};
+            // grouped so that no sum is shared with form 4: the compiler
+            // would hoist a shared a +- b above the form test
+            na = {(a.re - m.w0 * a.im) + b.re, (a.im + m.w0 * a.re) + b.im};
+            nb = {(a.re - m.w0 * b.im) - b.re, (a.im + m.w0 * b.re) - b.im};
         } else if (F == 2) {
             na = {m.m01 * b.re - m.w0 * a.im, m.m01 * b.im + m.w0 * a.re};
             nb = {m.m10 * a.re - m.w1 * b.im, m.m10 * a.im + m.w1 * b.re};
