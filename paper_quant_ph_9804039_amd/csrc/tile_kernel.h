@@ -494,31 +494,34 @@ k_tile(const TileArgs<R> A)
 #pragma unroll
         for (int i = 0; i < G; ++i)
             e[i] = e0[i];
-        apply_group<R, G>(A, group_first(A.group[0]), group_count(A.group[0]), x, j0, base,
-                          A.ngroups == 1);
-        for (uint32_t gi = 1; gi < A.ngroups; ++gi) {
-            // registers -> LDS in the old layout, LDS -> registers in the new one
-            if (pair0) {
+        // one call site of apply_group for all groups: its code (every
+        // operation case, twice for the two slots of a trip) is most of the
+        // kernel, and a second copy would double the instruction working set
+        for (uint32_t gi = 0; gi < A.ngroups; ++gi) {
+            if (gi > 0) {
+                // registers -> LDS in the old layout, LDS -> registers in the new one
+                if (pair0) {
 #pragma unroll
-                for (int r = 0; r < (1 << G); r += 2)
-                    st2(tile + elem_index<G>(j0, e, r), x[r], x[r + 1]);
-            } else {
+                    for (int r = 0; r < (1 << G); r += 2)
+                        st2(tile + elem_index<G>(j0, e, r), x[r], x[r + 1]);
+                } else {
 #pragma unroll
-                for (int r = 0; r < (1 << G); ++r)
-                    tile[elem_index<G>(j0, e, r)] = x[r];
+                    for (int r = 0; r < (1 << G); ++r)
+                        tile[elem_index<G>(j0, e, r)] = x[r];
+                }
+                __syncthreads();
+                group_layout<R, G>(A, gi, e, j0, pair0);
+                if (pair0) {
+#pragma unroll
+                    for (int r = 0; r < (1 << G); r += 2)
+                        ld2(tile + elem_index<G>(j0, e, r), x[r], x[r + 1]);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < (1 << G); ++r)
+                        x[r] = tile[elem_index<G>(j0, e, r)];
+                }
+                __syncthreads();
             }
-            __syncthreads();
-            group_layout<R, G>(A, gi, e, j0, pair0);
-            if (pair0) {
-#pragma unroll
-                for (int r = 0; r < (1 << G); r += 2)
-                    ld2(tile + elem_index<G>(j0, e, r), x[r], x[r + 1]);
-            } else {
-#pragma unroll
-                for (int r = 0; r < (1 << G); ++r)
-                    x[r] = tile[elem_index<G>(j0, e, r)];
-            }
-            __syncthreads();
             apply_group<R, G>(A, group_first(A.group[gi]), group_count(A.group[gi]), x, j0, base,
                               gi + 1 == A.ngroups);
         }
