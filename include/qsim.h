@@ -200,7 +200,11 @@ int qsim_set_amplitudes(qsim_state *s, uint64_t offset, uint64_t count, const do
  * qubits) is picked by timing each on one round of trials, once per
  * (register size, dtype, gate count, error kinds) and process, optionally
  * cached in the file QSIM_TUNE_CACHE names; QSIM_TRIAL_VARIANT = 0..3 forces
- * one where it can run. */
+ * one where it can run.  Device resources are kept per device between calls
+ * and held until the process ends: a stream, the error-free register (of the
+ * last shape run) and buffers grown to the largest call (about 64 bytes per
+ * gate and trial of a batch, at most ~256 MiB); calls on one device are
+ * serialised. */
 int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits, int dtype,
                     const qsim_error_model *base, uint64_t n_trials, double *out_F);
 

@@ -19,20 +19,6 @@ using namespace qsim;
 
 namespace {
 
-struct DevBuf {
-    void *p = nullptr;
-    ~DevBuf()
-    {
-        if (p)
-            (void)hipFree(p);
-    }
-};
-
-struct StateGuard {
-    qsim_state *s = nullptr;
-    ~StateGuard() { qsim_destroy(s); }
-};
-
 int hip_err(hipError_t e, const char *what)
 {
     (void)hipGetLastError();
@@ -144,17 +130,17 @@ void group_schedule(const qsim_gate *gates, size_t n, int M, int G, std::vector<
 
 // The register-group schedules on the device, one per group size.
 struct GroupSched {
-    DevBuf buf[2];  // G = 4, 5
+    void *buf[2] = {nullptr, nullptr};  // G = 4, 5 (device, not owned)
     uint32_t nchunks[2] = {0, 0}, ngroups[2] = {0, 0};
     void apply(TrialLaunch &L, int variant) const
     {
         const int G = trial_group_bits(variant);
-        if (G < 4 || G > 5 || buf[G - 4].p == nullptr) {
+        if (G < 4 || G > 5 || buf[G - 4] == nullptr) {
             L.sched = nullptr;
             L.nchunks = L.ngroups = 0;
             return;
         }
-        L.sched = reinterpret_cast<const uint32_t *>(buf[G - 4].p);
+        L.sched = reinterpret_cast<const uint32_t *>(buf[G - 4]);
         L.nchunks = nchunks[G - 4];
         L.ngroups = ngroups[G - 4];
     }
@@ -225,6 +211,55 @@ int autotune(int dtype, TrialLaunch L, const GroupSched &gs, hipStream_t st, dou
     return QSIM_OK;
 }
 
+// Device resources that qsim_run_trials keeps between calls, per device:
+// a stream, the error-free register's state, and buffers that grow to the
+// largest call seen.  They are held until the process ends (never freed at
+// exit, when the runtime may already be gone); calls on one device are
+// serialised by the workspace's mutex.
+struct Workspace {
+    std::mutex mu;
+    hipStream_t st = nullptr;
+    struct Buf {
+        void *p = nullptr;
+        size_t cap = 0;
+    };
+    Buf gates, out, sched[2], prep, prepx, tune;
+    qsim_state *ideal = nullptr;
+    int ideal_m = 0, ideal_dtype = -1;
+};
+
+hipError_t grow(Workspace::Buf &b, size_t bytes)
+{
+    bytes = std::max<size_t>(bytes, 1);
+    if (b.cap >= bytes)
+        return hipSuccess;
+    if (b.p != nullptr) {
+        // the previous call on this workspace ended with a stream sync
+        const hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        if (e != hipSuccess)
+            return e;
+    }
+    const hipError_t e = hipMalloc(&b.p, bytes);
+    if (e == hipSuccess)
+        b.cap = bytes;
+    else
+        b.p = nullptr;
+    return e;
+}
+
+Workspace &workspace(int device)
+{
+    static std::mutex mu;
+    static auto *all = new std::map<int, Workspace *>();  // never destroyed
+    std::lock_guard<std::mutex> lk(mu);
+    Workspace *&w = (*all)[device];
+    if (w == nullptr)
+        w = new Workspace();
+    return *w;
+}
+
 }  // namespace
 
 extern "C" int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits, int dtype,
@@ -255,21 +290,45 @@ extern "C" int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits,
     int device = 0;
     if (const char *d = getenv("QSIM_DEVICE"))
         device = atoi(d);
-    qsim_options o{};
-    o.device = device;
-    o.renorm_period = -1;
-    StateGuard ideal;
-    int rc = qsim_create(num_qubits, dtype, &o, &ideal.s);
+    Workspace &ws = workspace(device);
+    std::lock_guard<std::mutex> ws_lock(ws.mu);
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess)
+        return hip_err(e, "hipSetDevice");
+    if (ws.st == nullptr && (e = hipStreamCreateWithFlags(&ws.st, hipStreamNonBlocking)) != hipSuccess) {
+        ws.st = nullptr;
+        return hip_err(e, "stream");
+    }
+    hipStream_t st = ws.st;
+
+    // the error-free register, kept between calls of the same shape
+    int rc = QSIM_OK;
+    if (ws.ideal != nullptr && (ws.ideal_m != num_qubits || ws.ideal_dtype != dtype)) {
+        qsim_destroy(ws.ideal);
+        ws.ideal = nullptr;
+    }
+    if (ws.ideal == nullptr) {
+        qsim_options o{};
+        o.device = device;
+        o.renorm_period = -1;
+        rc = qsim_create(num_qubits, dtype, &o, &ws.ideal);
+        if (rc != QSIM_OK) {
+            ws.ideal = nullptr;
+            return rc;
+        }
+        ws.ideal_m = num_qubits;
+        ws.ideal_dtype = dtype;
+    } else if ((rc = qsim_reset(ws.ideal, 0)) != QSIM_OK) {
+        return rc;
+    }
+    rc = qsim_apply_circuit(ws.ideal, gates, n);
     if (rc != QSIM_OK)
         return rc;
-    rc = qsim_apply_circuit(ideal.s, gates, n);
-    if (rc != QSIM_OK)
-        return rc;
-    rc = qsim_synchronize(ideal.s);
+    rc = qsim_synchronize(ws.ideal);
     if (rc != QSIM_OK)
         return rc;
     void *ideal_ptr = nullptr;
-    rc = qsim_info(ideal.s, nullptr, nullptr, nullptr, &ideal_ptr, nullptr);
+    rc = qsim_info(ws.ideal, nullptr, nullptr, nullptr, &ideal_ptr, nullptr);
     if (rc != QSIM_OK)
         return rc;
 
@@ -286,23 +345,11 @@ extern "C" int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits,
         t.theta = gates[k].theta;
         hg[k] = t;
     }
-    hipError_t e = hipSetDevice(device);
-    if (e != hipSuccess)
-        return hip_err(e, "hipSetDevice");
-    hipStream_t st = nullptr;
-    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-    if (e != hipSuccess)
-        return hip_err(e, "stream");
-    struct StreamGuard {
-        hipStream_t s;
-        ~StreamGuard() { (void)hipStreamDestroy(s); }
-    } sg{st};
-    DevBuf dg, dout, dscratch;
-    if ((e = hipMalloc(&dg.p, std::max<size_t>(1, n) * sizeof(TrialGate))) != hipSuccess)
+    if ((e = grow(ws.gates, n * sizeof(TrialGate))) != hipSuccess)
         return hip_err(e, "gate buffer");
-    if ((e = hipMalloc(&dout.p, n_trials * sizeof(double))) != hipSuccess)
+    if ((e = grow(ws.out, n_trials * sizeof(double))) != hipSuccess)
         return hip_err(e, "output buffer");
-    if (n > 0 && (e = hipMemcpyAsync(dg.p, hg.data(), n * sizeof(TrialGate),
+    if (n > 0 && (e = hipMemcpyAsync(ws.gates.p, hg.data(), n * sizeof(TrialGate),
                                      hipMemcpyHostToDevice, st)) != hipSuccess)
         return hip_err(e, "gate upload");
     // register-group schedules (variants 2 and 3), where the register fits
@@ -314,32 +361,35 @@ extern "C" int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits,
         group_schedule(gates, n, num_qubits, G, sched[G - 4], gs.nchunks[G - 4],
                        gs.ngroups[G - 4]);
         const size_t bytes = sched[G - 4].size() * sizeof(uint32_t);
-        if ((e = hipMalloc(&gs.buf[G - 4].p, bytes)) != hipSuccess)
+        if ((e = grow(ws.sched[G - 4], bytes)) != hipSuccess)
             return hip_err(e, "schedule buffer");
-        if ((e = hipMemcpyAsync(gs.buf[G - 4].p, sched[G - 4].data(), bytes,
+        gs.buf[G - 4] = ws.sched[G - 4].p;
+        if ((e = hipMemcpyAsync(gs.buf[G - 4], sched[G - 4].data(), bytes,
                                 hipMemcpyHostToDevice, st)) != hipSuccess)
             return hip_err(e, "schedule upload");
     }
 
     // per-trial gate records of the register-group variants, a batch of
     // trials at a time (at most ~256 MiB)
-    DevBuf dprep, dprepx;
     uint64_t batch = 0;
-    if (gs.buf[0].p != nullptr || gs.buf[1].p != nullptr) {
+    void *prep = nullptr, *prepx = nullptr;
+    if (gs.buf[0] != nullptr || gs.buf[1] != nullptr) {
         const size_t per_trial = n * trial_gate_op_bytes(dtype == QSIM_C64 ? 8 : 16);
         const uint64_t cap = std::max<uint64_t>(1, ((size_t)256 << 20) / per_trial);
         batch = std::min<uint64_t>(cap, std::max<uint64_t>(n_trials, (uint64_t)kTuneTrials));
-        if ((e = hipMalloc(&dprep.p, batch * per_trial)) != hipSuccess)
+        if ((e = grow(ws.prep, batch * per_trial)) != hipSuccess)
             return hip_err(e, "trial gate buffer");
-        if ((e = hipMalloc(&dprepx.p, batch * sizeof(uint32_t))) != hipSuccess)
+        if ((e = grow(ws.prepx, batch * sizeof(uint32_t))) != hipSuccess)
             return hip_err(e, "trial mask buffer");
+        prep = ws.prep.p;
+        prepx = ws.prepx.p;
     }
 
     TrialLaunch L{};
-    L.prep_ops = dprep.p;
-    L.prep_X = reinterpret_cast<uint32_t *>(dprepx.p);
+    L.prep_ops = prep;
+    L.prep_X = reinterpret_cast<uint32_t *>(prepx);
     L.prep_batch = batch;
-    L.gates = reinterpret_cast<const TrialGate *>(dg.p);
+    L.gates = reinterpret_cast<const TrialGate *>(ws.gates.p);
     L.ngates = (uint32_t)n;
     L.M = (uint32_t)num_qubits;
     L.sigma = base->sigma;
@@ -370,11 +420,11 @@ extern "C" int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits,
             variant = forced;
     }
     if (variant < 0 || trial_grid(variant, num_qubits, elem) <= 0) {
-        if ((e = hipMalloc(&dscratch.p, kTuneTrials * sizeof(double))) != hipSuccess)
+        if ((e = grow(ws.tune, kTuneTrials * sizeof(double))) != hipSuccess)
             return hip_err(e, "tune buffer");
         TrialLaunch T = L;
         T.n_trials = 1;  // grid set per variant inside
-        rc = autotune(dtype, T, gs, st, reinterpret_cast<double *>(dscratch.p), variant);
+        rc = autotune(dtype, T, gs, st, reinterpret_cast<double *>(ws.tune.p), variant);
         if (rc != QSIM_OK)
             return rc;
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -386,10 +436,10 @@ extern "C" int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits,
     if (L.grid <= 0)
         return set_error(QSIM_EDEVICE, "trial kernel cannot run this register");
     L.n_trials = n_trials;
-    L.out_F = reinterpret_cast<double *>(dout.p);
+    L.out_F = reinterpret_cast<double *>(ws.out.p);
     if ((e = launch(dtype, L, st)) != hipSuccess)
         return hip_err(e, "trial launch");
-    if ((e = hipMemcpyAsync(out_F, dout.p, n_trials * sizeof(double), hipMemcpyDeviceToHost,
+    if ((e = hipMemcpyAsync(out_F, ws.out.p, n_trials * sizeof(double), hipMemcpyDeviceToHost,
                             st)) != hipSuccess)
         return hip_err(e, "result copy");
     if ((e = hipStreamSynchronize(st)) != hipSuccess)
