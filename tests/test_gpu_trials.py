@@ -112,3 +112,23 @@ def test_every_kernel_variant_matches_oracle(monkeypatch, variant, M, dtype, tol
                             em.trial, 12)
     assert np.max(np.abs(got - want)) < tol, np.max(np.abs(got - want))
     assert np.mean(want < 0.9) > 0.3
+
+
+def test_workspace_kept_between_calls_changes_no_result():
+    """The per-device workspace (error-free register, buffers grown to the
+    largest call) is reused across calls of different shapes and sizes: a
+    call repeated after others gives the same fidelities bit for bit, and a
+    larger batch starts with the smaller batch's trials."""
+    ga = cg.random_circuit(12, 150, 3)
+    gb = cg.random_circuit(13, 90, 4)
+    print("workspace reuse: M=12 c64 / M=13 c128 / M=12 c64", flush=True)
+    a1 = q.qsim_run_trials(ga, 12, q.QSIM_C64, 0.02, 1e-3, 1e-3, 8, 0, 48)
+    b1 = q.qsim_run_trials(gb, 13, q.QSIM_C128, 0.02, 1e-3, 1e-3, 9, 0, 16)
+    a2 = q.qsim_run_trials(ga, 12, q.QSIM_C64, 0.02, 1e-3, 1e-3, 8, 0, 48)
+    assert np.array_equal(a1, a2)
+    a3 = q.qsim_run_trials(ga, 12, q.QSIM_C64, 0.02, 1e-3, 1e-3, 8, 0, 1024)
+    assert np.array_equal(a3[:48], a1)
+    b2 = q.qsim_run_trials(gb, 13, q.QSIM_C128, 0.02, 1e-3, 1e-3, 9, 0, 16)
+    assert np.array_equal(b1, b2)
+    want = oracle.run_trials(gb, 13, oracle.Errors(0.02, 1e-3, 1e-3, 9, 0), 2)
+    assert np.max(np.abs(b2[:2] - want)) < 1e-12
