@@ -148,6 +148,33 @@ def bench_large(q, cg, np):
     return out
 
 
+def bench_structured(q, cg, np):
+    """The f(A) = 7^A mod 15 circuit (Sec. 2.2; 5 bits of A, H/X/CNOT/Toffoli)
+    on the top 9 qubits of an M=30 complex64 register, 16 times over: a
+    permutation-heavy workload whose targets are all high qubits.  Error-free
+    (the X-type gates are exact swaps) and with sigma = 1e-3."""
+    M = 30
+    one = cg.modexp15_circuit(5, qubit_map=list(range(M - 9, M)))
+    gates = np.concatenate([one] * 16)
+    out = {"gates": int(len(gates)), "num_qubits": M}
+    for name, sigma in (("error_free", 0.0), ("sigma_1e-3", SIGMA)):
+        with q.State(M, q.QSIM_C64) as s:
+            if sigma > 0.0:
+                s.inject_errors(sigma, 0.0, 0.0, seed=1415, trial=0)
+            s.apply(gates[:24])
+            s.synchronize()
+            s.profile(True)
+            t0 = time.perf_counter()
+            s.apply(gates)
+            s.synchronize()
+            wall = time.perf_counter() - t0
+            st = s.stats()
+        gbs = st["fused_bytes"] / (st["fused_ms"] * 1e-3) / 1e9 if st["fused_ms"] > 0 else None
+        out[name] = {"amplitude_updates_per_s": len(gates) * float(1 << M) / wall,
+                     "fused_passes": st["fused_passes"], "fused_GBps": gbs, "ms": wall * 1e3}
+    return out
+
+
 def bench_serving(q, cg, np, n_req: int = 80):
     """Poisson request stream (M in [10, 28], 100-2000 gates, sigma in
     {1e-4, 1e-3, 1e-2}, complex64): continuous batching against the same
@@ -301,6 +328,9 @@ def main() -> int:
     log("bench: 64 GiB registers")
     large = bench_large(q, cg, np)
     log(f"bench: large registers {json.dumps(large)}")
+    log("bench: structured workload (7^A mod 15 on the top qubits)")
+    structured = bench_structured(q, cg, np)
+    log(f"bench: structured {json.dumps(structured)}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -347,6 +377,7 @@ def main() -> int:
             "mc_trials": mc,
             "serving": serving,
             "large_register": large,
+            "structured_modexp15": structured,
         },
     }
     print(json.dumps(out), flush=True)

@@ -85,6 +85,43 @@ def ghz_circuit(num_qubits: int) -> np.ndarray:
     return gates_from_list(items)
 
 
+def modexp15_circuit(a_qubits: int = 4, qubit_map=None) -> np.ndarray:
+    """f(A) = 7^A mod 15 (Sec. 2.2, Fig. 4) on a register A of `a_qubits`
+    qubits (0 .. a_qubits-1) in uniform superposition and a 4-qubit register
+    y (qubits a_qubits .. a_qubits+3) prepared to 1, by repeated squaring
+    (EQ 1): bit l of A multiplies y by 7^(2^l) mod 15, which is 7, 4, then 1.
+
+    On 4-bit y in 1..14, multiplying by 2 mod 15 is a left rotation of the
+    bits (2^4 = 16 = 1 mod 15), so 4 = a rotation by two places (two swaps),
+    and 7 = -8 is a rotation by three places followed by the complement
+    (15 - y = NOT y).  A controlled swap is CNOT, Toffoli, CNOT; a controlled
+    complement is a CNOT per bit.  Gates: H, X, CNOT and Toffoli only.
+    qubit_map[i], if given, is the register qubit that logical qubit i uses."""
+    y = [a_qubits + i for i in range(4)]
+    items = [(H, q) for q in range(a_qubits)] + [(X, y[0])]
+
+    def cswap(c, p, q):
+        items.extend([(CNOT, p, q), (TOFFOLI, q, c, p), (CNOT, p, q)])
+
+    for l in range(a_qubits):
+        factor = pow(7, 1 << l, 15)
+        if factor == 7:  # rotate by three places (= right by one), then complement
+            cswap(l, y[0], y[1])
+            cswap(l, y[1], y[2])
+            cswap(l, y[2], y[3])
+            items.extend((CNOT, yi, l) for yi in y)
+        elif factor == 4:  # rotate by two places
+            cswap(l, y[0], y[2])
+            cswap(l, y[1], y[3])
+        # factor 1: nothing to do
+    if qubit_map is not None:
+        qm = [int(x) for x in qubit_map]
+        if len(qm) != a_qubits + 4 or len(set(qm)) != len(qm):
+            raise ValueError("qubit_map needs a_qubits + 4 distinct qubits")
+        items = [(it[0],) + tuple(qm[x] for x in it[1:]) for it in items]
+    return gates_from_list(items)
+
+
 def save_gates(path, gates: np.ndarray) -> None:
     np.ascontiguousarray(gates, dtype=GATE_DTYPE).tofile(path)
 

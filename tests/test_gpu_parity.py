@@ -351,3 +351,27 @@ def test_high_qubit_targets_vs_oracle(mode, dtype, tol_amp, tol_f):
     gates = cg.random_circuit(M, 300, 1018, top_bias=0.5)
     em = oracle.Errors(sigma=1e-3, p_bitflip=1e-4, p_phaseflip=1e-4, seed=1018, trial=0)
     _check_vs_oracle(M, gates, dtype, mode, em, tol_amp=tol_amp, tol_f=tol_f)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dtype,tol", [(q.QSIM_C128, 1e-13), (q.QSIM_C64, 1e-6)])
+def test_fig4_modexp_circuit(mode, dtype, tol):
+    """The f(A) = 7^A mod 15 circuit of Sec. 2.2 (a structured, permutation-
+    heavy workload; L + 1 = 5 bits of A): error-free, the distribution is
+    2^-5 on every |A>|7^A mod 15> (Fig. 4's period four); with errors it
+    matches the oracle."""
+    a_qubits = 5
+    M = a_qubits + 4
+    gates = cg.modexp15_circuit(a_qubits)
+    print(f"modexp 7^A mod 15 mode={mode} dtype={dtype}", flush=True)
+    want = np.zeros(1 << M)
+    for A in range(1 << a_qubits):
+        want[A | (pow(7, A, 15) << a_qubits)] = 1.0 / (1 << a_qubits)
+    with state(M, dtype, exec_mode=mode) as s:
+        s.apply(gates)
+        p = s.probs((1 << M) - 1)
+        assert np.max(np.abs(p - want)) < tol
+    em = oracle.Errors(sigma=0.02, p_bitflip=2e-3, p_phaseflip=2e-3, seed=415, trial=3)
+    _check_vs_oracle(M, gates, dtype, mode, em,
+                     tol_amp=1e-12 if dtype == q.QSIM_C128 else 2e-5,
+                     tol_f=1e-12 if dtype == q.QSIM_C128 else 1e-6)

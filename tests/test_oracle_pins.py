@@ -417,3 +417,21 @@ def test_invalid_inputs_rejected():
             oracle.simulate(3, cg.gates_from_list(items))
     with pytest.raises(ValueError):
         oracle.simulate(3, cg.gates_from_list([(cg.H, 0)]), oracle.Errors(p_bitflip=1.5))
+
+
+@pytest.mark.parametrize("a_qubits", [4, 5])
+def test_fig4_modexp_7_mod_15_has_period_four(a_qubits):
+    """Sec. 2.2 / Fig. 4 / EQ 1: the f(A) circuit (repeated squaring, X = 7,
+    N = 15) on A in uniform superposition leaves |A>|7^A mod 15> with
+    probability 2^-a for every A, and f repeats with period four (L + 1 = 5
+    bits of A as in Sec. 2.2.1, or 4)."""
+    M = a_qubits + 4
+    gates = cg.modexp15_circuit(a_qubits)
+    assert set(int(k) for k in gates["kind"]) <= {cg.H, cg.X, cg.CNOT, cg.TOFFOLI}
+    p = np.abs(oracle.as_complex(oracle.simulate(M, gates))) ** 2
+    want = np.zeros(1 << M)
+    for A in range(1 << a_qubits):
+        want[A | (pow(7, A, 15) << a_qubits)] = 1.0 / (1 << a_qubits)
+    assert np.max(np.abs(p - want)) < 1e-15
+    f = [pow(7, A, 15) for A in range(1 << a_qubits)]
+    assert f[:4] == [1, 7, 4, 13] and all(f[A] == f[A % 4] for A in range(len(f)))
