@@ -92,7 +92,9 @@ __device__ void gate_matrix(uint32_t kind, double theta, double eps, uint32_t &t
 // (built by the preparation kernel for the group the gate sits in):
 //   meta  = type | form << 4 | neg_val << 8 | P << 12 | target << 16, P =
 //           the target's position among the group qubits, 15 when it is not
-//           one;
+//           one; forms 0-3 as in TrialOp, and for an uncontrolled Hadamard 4
+//           = the butterfly (a + b, a - b) and 5 = (b - a, a + b), each plus
+//           i t on the diagonal with t = u[0].im (the scale dropped);
 //   regs  = rm | rv << 8 | rz << 16: controls on group qubits and the values
 //           they need, and phase flips on group qubits, over the register
 //           index;
@@ -370,6 +372,16 @@ __device__ __forceinline__ void trial_pair(const cplx<R> (&u)[4], uint32_t rm, u
         } else if (F == 2) {
             x[r] = {u[1].re * b.re - u[0].im * a.im, u[1].re * b.im + u[0].im * a.re};
             x[r1] = {u[2].re * a.re - u[3].im * b.im, u[2].re * a.im + u[3].im * b.re};
+        } else if (F == 4) {
+            // a + b, a - b plus i t on the diagonal (no sum shared with F = 5)
+            const R t = u[0].im;
+            x[r] = {(a.re - t * a.im) + b.re, (a.im + t * a.re) + b.im};
+            x[r1] = {(a.re - t * b.im) - b.re, (a.im + t * b.re) - b.im};
+        } else if (F == 5) {
+            // b - a, a + b plus i t on the diagonal
+            const R t = u[0].im;
+            x[r] = {(b.re - t * a.im) - a.re, (b.im + t * a.re) - a.im};
+            x[r1] = {(b.re - t * b.im) + a.re, (b.im + t * b.re) + a.im};
         } else {
             x[r] = cmad2(u[0], a, u[1], b);
             x[r1] = cmad2(u[2], a, u[3], b);
@@ -480,6 +492,8 @@ __device__ __forceinline__ void trial_at(uint32_t type, uint32_t form, uint32_t 
     case 0: trial_pair<R, G, P, 0, false>(u, rm, rv, x); break;
     case 1: trial_pair<R, G, P, 1, false>(u, rm, rv, x); break;
     case 2: trial_pair<R, G, P, 2, false>(u, rm, rv, x); break;
+    case 4: trial_pair<R, G, P, 4, false>(u, rm, rv, x); break;  // never controlled
+    case 5: trial_pair<R, G, P, 5, false>(u, rm, rv, x); break;
     default: trial_pair<R, G, P, 3, false>(u, rm, rv, x); break;
     }
 }
@@ -634,7 +648,17 @@ __global__ void __launch_bounds__(kPrepThreads) k_trial_prep(const TrialLaunch L
             const bool real_off = u[3] == 0.0 && u[5] == 0.0;
             const bool real_diag = u[1] == 0.0 && u[7] == 0.0;
             const bool zero_diag = u[0] == 0.0 && u[6] == 0.0;
-            const uint32_t form = !real_off ? 3u : real_diag ? 0u : zero_diag ? 2u : 1u;
+            uint32_t form = !real_off ? 3u : real_diag ? 0u : zero_diag ? 2u : 1u;
+            // an uncontrolled Hadamard, perturbed or not, is h (B + i t) with
+            // B = [[1, 1], [1, -1]], or [[-1, 1], [1, 1]] after X U X; the
+            // real scale h does not change the trial's fidelity, so the pair
+            // update is the butterfly B plus i t on the diagonal (t in u[0].im)
+            const double hb = u[2];
+            if (type == kOpMat && gd.cmask == 0 && real_off && hb != 0.0 && u[4] == hb &&
+                u[1] == u[7] && ((u[0] == hb && u[6] == -hb) || (u[0] == -hb && u[6] == hb))) {
+                form = u[0] == hb ? 4u : 5u;
+                op.u[0].im = (R)(u[1] / hb);
+            }
             // positions relative to the gate's group
             const uint32_t w = gword[g];
             const uint32_t cval = gd.cmask & ~xg;
