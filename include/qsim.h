@@ -36,7 +36,9 @@
  * Different states may be used concurrently.  Error messages are per thread.
  *
  * Return values: QSIM_OK (0) or a negative status.  On QSIM_EINVAL nothing
- * has been written or launched.  No function aborts or throws.
+ * has been written or launched.  No function aborts or throws: host memory
+ * exhaustion inside a call is reported as QSIM_ENOMEM, any other internal
+ * failure as QSIM_EDEVICE, with the message in qsim_last_error().
  */
 #ifndef QSIM_INCLUDE_QSIM_API_H_
 #define QSIM_INCLUDE_QSIM_API_H_
@@ -139,8 +141,9 @@ int qsim_create(int num_qubits, int dtype, const qsim_options *opt, qsim_state *
  * stream (unless borrowed).  NULL is accepted. */
 int qsim_destroy(qsim_state *s);
 
-/* Set the state to the basis state |basis_index> and the step counter to 0.
- * ERANGE if basis_index >= 2^M. */
+/* Set the state to the basis state |basis_index> (Sec. 1.2, Fig. 1(a): one
+ * amplitude 1, every other 0) and the step counter to 0; the armed error
+ * model stays armed.  ERANGE if basis_index >= 2^M. */
 int qsim_reset(qsim_state *s, uint64_t basis_index);
 
 /* Apply gates[0..n_gates) in order (Sec. 2.1), each followed by the armed
@@ -157,13 +160,23 @@ int qsim_apply_circuit(qsim_state *s, const qsim_gate *gates, size_t n_gates);
 int qsim_apply_inverse(qsim_state *s, const qsim_gate *gates, size_t n_gates);
 
 /* Arm the error model for later apply_circuit calls (copied), or disarm it
- * with NULL.  With sigma = 0 and both p = 0 the run is bit-identical to a run
- * with errors disarmed.  EINVAL for negative/non-finite sigma or p outside
- * [0, 1]. */
+ * with NULL.  Errors are injected at every step (Sec. 1.0): the angle of each
+ * gate deviates by eps = sigma * z (Sec. 1.4 and 2.0: operational errors are
+ * deviations of the rotation angles), and after each gate every qubit takes a
+ * bit flip and then a phase flip with probabilities p_bitflip and
+ * p_phaseflip (Sec. 3.4 and EQ 8: two extra transformations after every
+ * operation model decoherence).  Arming draws nothing: the draws of a gate
+ * depend only on (seed, trial, step), so a circuit split over several
+ * apply_circuit calls gets the same errors.  With sigma = 0 and both p = 0
+ * the run is bit-identical to a run with errors disarmed.  EINVAL for
+ * negative/non-finite sigma or p outside [0, 1]. */
 int qsim_inject_errors(qsim_state *s, const qsim_error_model *em);
 
 /* F = |<a|b>|^2 / (<a|a> <b|b>), accumulated in FP64 on the device with a
- * fixed reduction order (deterministic).  a and b must have the same M; their
+ * fixed reduction order (deterministic).  The paper tracks how errors
+ * accumulate (Sec. 1.0) but defines no fidelity; this normalised squared
+ * overlap is the library's choice: it equals |<a|b>|^2 for unit vectors and
+ * ignores norm drift and global phase.  a and b must have the same M; their
  * dtypes may differ.  Synchronises both states' streams. */
 int qsim_fidelity(const qsim_state *a, const qsim_state *b, double *out_F);
 
@@ -188,10 +201,13 @@ int qsim_get_amplitudes(const qsim_state *s, uint64_t offset, uint64_t count, do
  * memory (rounded to the state's dtype).  Does not touch the step counter. */
 int qsim_set_amplitudes(qsim_state *s, uint64_t offset, uint64_t count, const double *in);
 
-/* Batched Monte Carlo: the error-free run of gates[0..n) from |0...0> is the
+/* Batched Monte Carlo (Sec. 1.0: errors injected at each step, their
+ * accumulation tracked; Sec. 1.4, 2.0 and 3.4 for the error model, as in
+ * qsim_inject_errors): the error-free run of gates[0..n) from |0...0> is the
  * reference; trial t (0 <= t < n_trials) runs the same circuit from |0...0>
  * with error model `base` keyed by trial base->trial + t, and out_F[t] is its
- * fidelity against the reference (host memory, n_trials doubles).  All trials
+ * fidelity against the reference (host memory, n_trials doubles; the same
+ * value qsim_fidelity gives for two registers run that way).  All trials
  * run in one persistent launch, one register per workgroup, which needs the
  * register to fit the workgroup's LDS (num_qubits <= 14 for QSIM_C64,
  * <= 13 for QSIM_C128); EINVAL beyond that.  Synchronous.  Runs on `device`
@@ -207,6 +223,21 @@ int qsim_set_amplitudes(qsim_state *s, uint64_t offset, uint64_t count, const do
  * serialised. */
 int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits, int dtype,
                     const qsim_error_model *base, uint64_t n_trials, double *out_F);
+
+/* Host-only dry run of the register-group schedule qsim_run_trials uses when
+ * each thread holds group_bits (4 or 5) qubits of a trial's register: the
+ * circuit is cut into groups of consecutive gates whose non-diagonal targets
+ * fall on at most group_bits qubits (Sec. 2.1: a gate only mixes the pairs of
+ * its target, so such a run is a fixed pattern of register pairs) and that
+ * hold at most 32 uncontrolled Hadamards (the kernel applies their real scale
+ * at the group's end).  Writes min(cap, groups) records of 4 words to out:
+ * first gate, gate count, mask of the group's qubits, uncontrolled Hadamards
+ * in the group; and the group count to *n_groups (either may be NULL).  No
+ * device is used.  EINVAL for a bad gate, group_bits, or a register the
+ * register-group kernels cannot hold (num_qubits - group_bits outside
+ * [6, 10]). */
+int qsim_trial_plan(const qsim_gate *gates, size_t n, int num_qubits, int group_bits,
+                    uint32_t *out, size_t cap, size_t *n_groups);
 
 /* One pass of a fused schedule (qsim_plan). */
 typedef struct {

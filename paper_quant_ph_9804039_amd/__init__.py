@@ -33,6 +33,7 @@ EXPORTED = [
     "qsim_inject_errors", "qsim_fidelity", "qsim_overlap", "qsim_norm", "qsim_probs",
     "qsim_get_amplitudes", "qsim_set_amplitudes", "qsim_run_trials", "qsim_synchronize",
     "qsim_info", "qsim_profile", "qsim_get_stats", "qsim_last_error", "qsim_plan", "qsim_serve",
+    "qsim_trial_plan",
 ]
 
 
@@ -132,6 +133,8 @@ def lib() -> ctypes.CDLL:
                       ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_uint32), sz],
         "qsim_serve": [ctypes.POINTER(qsim_request), sz, ctypes.POINTER(qsim_serve_options),
                        ctypes.POINTER(qsim_result)],
+        "qsim_trial_plan": [vp, sz, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint32),
+                            sz, ctypes.POINTER(sz)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -302,6 +305,21 @@ def qsim_plan(num_qubits: int, dtype: int, gates, options: qsim_options | None =
     if return_order:
         return passes, nops.value, order[:nops.value]
     return passes, nops.value
+
+
+def qsim_trial_plan(gates, num_qubits: int, group_bits: int) -> np.ndarray:
+    """Host-only dry run of the Monte Carlo register-group schedule: one row
+    per group, (first gate, gate count, qubit mask, uncontrolled Hadamards)."""
+    g = _gates(gates)
+    n = ctypes.c_size_t()
+    L = lib()
+    _check(L.qsim_trial_plan(g.ctypes.data, len(g), num_qubits, group_bits, None, 0,
+                             ctypes.byref(n)))
+    out = np.zeros((max(1, n.value), 4), dtype=np.uint32)
+    _check(L.qsim_trial_plan(g.ctypes.data, len(g), num_qubits, group_bits,
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), n.value,
+                             ctypes.byref(n)))
+    return out[:n.value]
 
 
 def qsim_serve(requests, max_slots: int = 8, hbm_budget: int = 0, strict_fifo: bool = False,

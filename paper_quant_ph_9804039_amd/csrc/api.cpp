@@ -23,16 +23,16 @@ using namespace qsim;
 
 namespace {
 
-thread_local std::string g_err;
+// Message of the last failing call, per thread (a fixed buffer, so that
+// recording an error never allocates).
+thread_local char g_err[512];
 
 int fail(int code, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
@@ -63,12 +63,10 @@ namespace qsim {
 
 int set_error(int code, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
@@ -1043,7 +1041,9 @@ namespace qsim {
 int slot_state_create(int device, hipStream_t st, int max_qubits, qsim_state **out)
 {
     *out = nullptr;
-    qsim_state *s = new qsim_state();
+    qsim_state *s = new (std::nothrow) qsim_state();
+    if (s == nullptr)
+        return fail(QSIM_ENOMEM, "slot state: host memory exhausted");
     s->device = device;
     s->stream = st;
     s->own_stream = false;
@@ -1116,355 +1116,383 @@ void slot_state_destroy(qsim_state *s) { release(s); }
 
 extern "C" {
 
-const char *qsim_last_error(void) { return g_err.c_str(); }
+const char *qsim_last_error(void) { return g_err; }
 
 int qsim_create(int num_qubits, int dtype, const qsim_options *opt, qsim_state **out)
 {
-    if (out == nullptr)
-        return fail(QSIM_EINVAL, "out is NULL");
-    *out = nullptr;
-    qsim_options o{};
-    if (opt)
-        o = *opt;
-    qsim_state *s = new qsim_state();
-    int rc = configure(s, num_qubits, dtype, o);
-    if (rc != QSIM_OK) {
-        delete s;
-        return rc;
-    }
-    const size_t bytes = s->bytes;
-    const int k = s->tile_bits;
-    int ndev = 0;
-    hipError_t e0 = hipGetDeviceCount(&ndev);
-    if (e0 != hipSuccess) {
-        delete s;
-        return hip_fail(e0, "hipGetDeviceCount");
-    }
-    if (o.device < 0 || o.device >= ndev) {
-        delete s;
-        return fail(QSIM_EINVAL, "device %d outside [0, %d)", o.device, ndev);
-    }
-    hipError_t e = hipSetDevice(o.device);
-    if (e == hipSuccess) {
-        if (o.hip_stream) {
-            s->stream = reinterpret_cast<hipStream_t>(o.hip_stream);
-        } else {
-            e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-            s->own_stream = e == hipSuccess;
+    return guarded(__func__, [&]() -> int {
+        if (out == nullptr)
+            return fail(QSIM_EINVAL, "out is NULL");
+        *out = nullptr;
+        qsim_options o{};
+        if (opt)
+            o = *opt;
+        qsim_state *s = new (std::nothrow) qsim_state();
+        if (s == nullptr)
+            return fail(QSIM_ENOMEM, "qsim_create: host memory exhausted");
+        int rc = configure(s, num_qubits, dtype, o);
+        if (rc != QSIM_OK) {
+            delete s;
+            return rc;
         }
-    }
-    if (e == hipSuccess) {
-        if (o.ext_buffer) {
-            s->psi = o.ext_buffer;
-        } else {
-            e = hipMalloc(&s->psi, bytes);
-            s->own_mem = e == hipSuccess;
+        const size_t bytes = s->bytes;
+        const int k = s->tile_bits;
+        int ndev = 0;
+        hipError_t e0 = hipGetDeviceCount(&ndev);
+        if (e0 != hipSuccess) {
+            delete s;
+            return hip_fail(e0, "hipGetDeviceCount");
         }
-    }
-    const int kk = std::min(k, num_qubits);
-    const uint64_t tiles = 1ull << (num_qubits - kk);
-    if (e == hipSuccess)
-        e = hipMalloc((void **)&s->d_partial, 4 * kReduceBlocks * sizeof(double));
-    if (e == hipSuccess)
-        e = hipMalloc((void **)&s->d_tile_norm, tiles * sizeof(double));
-    if (e == hipSuccess)
-        e = hipMalloc((void **)&s->d_scalars, 16 * sizeof(double));
-    if (e == hipSuccess)
-        e = hipHostMalloc((void **)&s->h_pinned, 16 * sizeof(double), hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = (dtype == QSIM_C64)
-                ? launch_init_basis<float>((cplx<float> *)s->psi, num_qubits, 0, s->stream)
-                : launch_init_basis<double>((cplx<double> *)s->psi, num_qubits, 0, s->stream);
-    if (e != hipSuccess) {
-        rc = hip_fail(e, "qsim_create");
-        release(s);
-        return rc;
-    }
-    *out = s;
-    return QSIM_OK;
+        if (o.device < 0 || o.device >= ndev) {
+            delete s;
+            return fail(QSIM_EINVAL, "device %d outside [0, %d)", o.device, ndev);
+        }
+        hipError_t e = hipSetDevice(o.device);
+        if (e == hipSuccess) {
+            if (o.hip_stream) {
+                s->stream = reinterpret_cast<hipStream_t>(o.hip_stream);
+            } else {
+                e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+                s->own_stream = e == hipSuccess;
+            }
+        }
+        if (e == hipSuccess) {
+            if (o.ext_buffer) {
+                s->psi = o.ext_buffer;
+            } else {
+                e = hipMalloc(&s->psi, bytes);
+                s->own_mem = e == hipSuccess;
+            }
+        }
+        const int kk = std::min(k, num_qubits);
+        const uint64_t tiles = 1ull << (num_qubits - kk);
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&s->d_partial, 4 * kReduceBlocks * sizeof(double));
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&s->d_tile_norm, tiles * sizeof(double));
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&s->d_scalars, 16 * sizeof(double));
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&s->h_pinned, 16 * sizeof(double), hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = (dtype == QSIM_C64)
+                    ? launch_init_basis<float>((cplx<float> *)s->psi, num_qubits, 0, s->stream)
+                    : launch_init_basis<double>((cplx<double> *)s->psi, num_qubits, 0, s->stream);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "qsim_create");
+            release(s);
+            return rc;
+        }
+        *out = s;
+        return QSIM_OK;
+    });
 }
 
 int qsim_destroy(qsim_state *s)
 {
-    release(s);
-    return QSIM_OK;
+    return guarded(__func__, [&]() -> int {
+        release(s);
+        return QSIM_OK;
+    });
 }
 
 int qsim_reset(qsim_state *s, uint64_t basis_index)
 {
-    if (s == nullptr)
-        return fail(QSIM_EINVAL, "state is NULL");
-    if (basis_index >= (1ull << s->M))
-        return fail(QSIM_ERANGE, "basis index %llu >= 2^%d", (unsigned long long)basis_index, s->M);
-    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
-    Timed t(s, 2, 0);
-    HIP_TRY(s->dtype == QSIM_C64
-                ? launch_init_basis<float>((cplx<float> *)s->psi, s->M, basis_index, s->stream)
-                : launch_init_basis<double>((cplx<double> *)s->psi, s->M, basis_index, s->stream),
-            "init launch");
-    t.done();
-    s->step = 0;
-    return QSIM_OK;
+    return guarded(__func__, [&]() -> int {
+        if (s == nullptr)
+            return fail(QSIM_EINVAL, "state is NULL");
+        if (basis_index >= (1ull << s->M))
+            return fail(QSIM_ERANGE, "basis index %llu >= 2^%d", (unsigned long long)basis_index, s->M);
+        HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+        Timed t(s, 2, 0);
+        HIP_TRY(s->dtype == QSIM_C64
+                    ? launch_init_basis<float>((cplx<float> *)s->psi, s->M, basis_index, s->stream)
+                    : launch_init_basis<double>((cplx<double> *)s->psi, s->M, basis_index, s->stream),
+                "init launch");
+        t.done();
+        s->step = 0;
+        return QSIM_OK;
+    });
 }
 
 int qsim_inject_errors(qsim_state *s, const qsim_error_model *em)
 {
-    if (s == nullptr)
-        return fail(QSIM_EINVAL, "state is NULL");
-    if (em == nullptr) {
-        s->armed = false;
+    return guarded(__func__, [&]() -> int {
+        if (s == nullptr)
+            return fail(QSIM_EINVAL, "state is NULL");
+        if (em == nullptr) {
+            s->armed = false;
+            return QSIM_OK;
+        }
+        if (!error_model_valid(*em))
+            return fail(QSIM_EINVAL, "sigma must be finite and >= 0, flip probabilities in [0, 1]");
+        s->em = *em;
+        s->armed = true;
         return QSIM_OK;
-    }
-    if (!error_model_valid(*em))
-        return fail(QSIM_EINVAL, "sigma must be finite and >= 0, flip probabilities in [0, 1]");
-    s->em = *em;
-    s->armed = true;
-    return QSIM_OK;
+    });
 }
 
 int qsim_apply_circuit(qsim_state *s, const qsim_gate *gates, size_t n_gates)
 {
-    if (s == nullptr)
-        return fail(QSIM_EINVAL, "state is NULL");
-    int rc = validate_gates(s, gates, n_gates);
-    if (rc != QSIM_OK)
-        return rc;
-    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
-    std::vector<Op> ops;
-    lower_circuit(s, gates, n_gates, ops);
-    rc = s->dtype == QSIM_C64 ? run_ops<float>(s, ops) : run_ops<double>(s, ops);
-    if (rc != QSIM_OK)
-        return rc;
-    s->step += n_gates;
-    s->stats.gates += n_gates;
-    s->stats.flips += ops.size() - n_gates;
-    return QSIM_OK;
+    return guarded(__func__, [&]() -> int {
+        if (s == nullptr)
+            return fail(QSIM_EINVAL, "state is NULL");
+        int rc = validate_gates(s, gates, n_gates);
+        if (rc != QSIM_OK)
+            return rc;
+        HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+        std::vector<Op> ops;
+        lower_circuit(s, gates, n_gates, ops);
+        rc = s->dtype == QSIM_C64 ? run_ops<float>(s, ops) : run_ops<double>(s, ops);
+        if (rc != QSIM_OK)
+            return rc;
+        s->step += n_gates;
+        s->stats.gates += n_gates;
+        s->stats.flips += ops.size() - n_gates;
+        return QSIM_OK;
+    });
 }
 
 int qsim_apply_inverse(qsim_state *s, const qsim_gate *gates, size_t n_gates)
 {
-    if (s == nullptr)
-        return fail(QSIM_EINVAL, "state is NULL");
-    int rc = validate_gates(s, gates, n_gates);
-    if (rc != QSIM_OK)
+    return guarded(__func__, [&]() -> int {
+        if (s == nullptr)
+            return fail(QSIM_EINVAL, "state is NULL");
+        int rc = validate_gates(s, gates, n_gates);
+        if (rc != QSIM_OK)
+            return rc;
+        HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+        std::vector<Op> ops;
+        ops.reserve(n_gates);
+        for (size_t k = 0; k < n_gates; ++k) {
+            Op op = lower_gate(gates[n_gates - 1 - k], 0.0, true);
+            op.step = k;
+            op.is_flip = false;
+            op.step_end = true;
+            ops.push_back(op);
+        }
+        const int saved = s->renorm_period;
+        s->renorm_period = 0;
+        rc = s->dtype == QSIM_C64 ? run_ops<float>(s, ops) : run_ops<double>(s, ops);
+        s->renorm_period = saved;
         return rc;
-    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
-    std::vector<Op> ops;
-    ops.reserve(n_gates);
-    for (size_t k = 0; k < n_gates; ++k) {
-        Op op = lower_gate(gates[n_gates - 1 - k], 0.0, true);
-        op.step = k;
-        op.is_flip = false;
-        op.step_end = true;
-        ops.push_back(op);
-    }
-    const int saved = s->renorm_period;
-    s->renorm_period = 0;
-    rc = s->dtype == QSIM_C64 ? run_ops<float>(s, ops) : run_ops<double>(s, ops);
-    s->renorm_period = saved;
-    return rc;
+    });
 }
 
 int qsim_synchronize(qsim_state *s)
 {
-    if (s == nullptr)
-        return fail(QSIM_EINVAL, "state is NULL");
-    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
-    HIP_TRY(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-    return QSIM_OK;
+    return guarded(__func__, [&]() -> int {
+        if (s == nullptr)
+            return fail(QSIM_EINVAL, "state is NULL");
+        HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+        HIP_TRY(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        return QSIM_OK;
+    });
 }
 
 int qsim_overlap(const qsim_state *a, const qsim_state *b, double out[4])
 {
-    if (a == nullptr || b == nullptr || out == nullptr)
-        return fail(QSIM_EINVAL, "NULL argument");
-    if (a->M != b->M)
-        return fail(QSIM_EINVAL, "register sizes differ (%d vs %d)", a->M, b->M);
-    if (a->device != b->device)
-        return fail(QSIM_EINVAL, "states live on different devices");
-    qsim_state *sa = const_cast<qsim_state *>(a);
-    HIP_TRY(hipSetDevice(a->device), "hipSetDevice");
-    if (a->stream != b->stream) {
-        hipEvent_t ev;
-        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
-        HIP_TRY(hipEventRecord(ev, b->stream), "event record");
-        HIP_TRY(hipStreamWaitEvent(a->stream, ev, 0), "stream wait");
-        (void)hipEventDestroy(ev);
-    }
-    Timed t(sa, 2, 0);
-    hipError_t e;
-    if (a->dtype == QSIM_C64 && b->dtype == QSIM_C64)
-        e = launch_overlap<float, float>((const cplx<float> *)a->psi, (const cplx<float> *)b->psi,
-                                         a->M, a->d_partial, a->d_scalars, a->stream);
-    else if (a->dtype == QSIM_C64)
-        e = launch_overlap<float, double>((const cplx<float> *)a->psi,
-                                          (const cplx<double> *)b->psi, a->M, a->d_partial,
-                                          a->d_scalars, a->stream);
-    else if (b->dtype == QSIM_C64)
-        e = launch_overlap<double, float>((const cplx<double> *)a->psi,
-                                          (const cplx<float> *)b->psi, a->M, a->d_partial,
-                                          a->d_scalars, a->stream);
-    else
-        e = launch_overlap<double, double>((const cplx<double> *)a->psi,
-                                           (const cplx<double> *)b->psi, a->M, a->d_partial,
-                                           a->d_scalars, a->stream);
-    HIP_TRY(e, "overlap launch");
-    t.done();
-    HIP_TRY(hipMemcpyAsync(a->h_pinned, a->d_scalars, 4 * sizeof(double), hipMemcpyDeviceToHost,
-                           a->stream), "overlap copy");
-    HIP_TRY(hipStreamSynchronize(a->stream), "overlap sync");
-    if (a->stream != b->stream)
-        HIP_TRY(hipStreamSynchronize(b->stream), "overlap sync");
-    std::memcpy(out, a->h_pinned, 4 * sizeof(double));
-    return QSIM_OK;
+    return guarded(__func__, [&]() -> int {
+        if (a == nullptr || b == nullptr || out == nullptr)
+            return fail(QSIM_EINVAL, "NULL argument");
+        if (a->M != b->M)
+            return fail(QSIM_EINVAL, "register sizes differ (%d vs %d)", a->M, b->M);
+        if (a->device != b->device)
+            return fail(QSIM_EINVAL, "states live on different devices");
+        qsim_state *sa = const_cast<qsim_state *>(a);
+        HIP_TRY(hipSetDevice(a->device), "hipSetDevice");
+        if (a->stream != b->stream) {
+            hipEvent_t ev;
+            HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+            HIP_TRY(hipEventRecord(ev, b->stream), "event record");
+            HIP_TRY(hipStreamWaitEvent(a->stream, ev, 0), "stream wait");
+            (void)hipEventDestroy(ev);
+        }
+        Timed t(sa, 2, 0);
+        hipError_t e;
+        if (a->dtype == QSIM_C64 && b->dtype == QSIM_C64)
+            e = launch_overlap<float, float>((const cplx<float> *)a->psi, (const cplx<float> *)b->psi,
+                                             a->M, a->d_partial, a->d_scalars, a->stream);
+        else if (a->dtype == QSIM_C64)
+            e = launch_overlap<float, double>((const cplx<float> *)a->psi,
+                                              (const cplx<double> *)b->psi, a->M, a->d_partial,
+                                              a->d_scalars, a->stream);
+        else if (b->dtype == QSIM_C64)
+            e = launch_overlap<double, float>((const cplx<double> *)a->psi,
+                                              (const cplx<float> *)b->psi, a->M, a->d_partial,
+                                              a->d_scalars, a->stream);
+        else
+            e = launch_overlap<double, double>((const cplx<double> *)a->psi,
+                                               (const cplx<double> *)b->psi, a->M, a->d_partial,
+                                               a->d_scalars, a->stream);
+        HIP_TRY(e, "overlap launch");
+        t.done();
+        HIP_TRY(hipMemcpyAsync(a->h_pinned, a->d_scalars, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                               a->stream), "overlap copy");
+        HIP_TRY(hipStreamSynchronize(a->stream), "overlap sync");
+        if (a->stream != b->stream)
+            HIP_TRY(hipStreamSynchronize(b->stream), "overlap sync");
+        std::memcpy(out, a->h_pinned, 4 * sizeof(double));
+        return QSIM_OK;
+    });
 }
 
 int qsim_fidelity(const qsim_state *a, const qsim_state *b, double *out_F)
 {
-    if (out_F == nullptr)
-        return fail(QSIM_EINVAL, "out_F is NULL");
-    double o[4];
-    int rc = qsim_overlap(a, b, o);
-    if (rc != QSIM_OK)
-        return rc;
-    *out_F = (o[0] * o[0] + o[1] * o[1]) / (o[2] * o[3]);
-    return QSIM_OK;
+    return guarded(__func__, [&]() -> int {
+        if (out_F == nullptr)
+            return fail(QSIM_EINVAL, "out_F is NULL");
+        double o[4];
+        int rc = qsim_overlap(a, b, o);
+        if (rc != QSIM_OK)
+            return rc;
+        *out_F = (o[0] * o[0] + o[1] * o[1]) / (o[2] * o[3]);
+        return QSIM_OK;
+    });
 }
 
 int qsim_norm(const qsim_state *s, double *out)
 {
-    if (s == nullptr || out == nullptr)
-        return fail(QSIM_EINVAL, "NULL argument");
-    qsim_state *m = const_cast<qsim_state *>(s);
-    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
-    Timed t(m, 2, 0);
-    HIP_TRY(s->dtype == QSIM_C64
-                ? launch_norm<float>((const cplx<float> *)s->psi, s->M, s->d_partial,
-                                     s->d_scalars, s->stream)
-                : launch_norm<double>((const cplx<double> *)s->psi, s->M, s->d_partial,
-                                      s->d_scalars, s->stream),
-            "norm launch");
-    t.done();
-    HIP_TRY(hipMemcpyAsync(s->h_pinned, s->d_scalars, 4 * sizeof(double), hipMemcpyDeviceToHost,
-                           s->stream), "norm copy");
-    HIP_TRY(hipStreamSynchronize(s->stream), "norm sync");
-    *out = s->h_pinned[2];
-    return QSIM_OK;
+    return guarded(__func__, [&]() -> int {
+        if (s == nullptr || out == nullptr)
+            return fail(QSIM_EINVAL, "NULL argument");
+        qsim_state *m = const_cast<qsim_state *>(s);
+        HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+        Timed t(m, 2, 0);
+        HIP_TRY(s->dtype == QSIM_C64
+                    ? launch_norm<float>((const cplx<float> *)s->psi, s->M, s->d_partial,
+                                         s->d_scalars, s->stream)
+                    : launch_norm<double>((const cplx<double> *)s->psi, s->M, s->d_partial,
+                                          s->d_scalars, s->stream),
+                "norm launch");
+        t.done();
+        HIP_TRY(hipMemcpyAsync(s->h_pinned, s->d_scalars, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                               s->stream), "norm copy");
+        HIP_TRY(hipStreamSynchronize(s->stream), "norm sync");
+        *out = s->h_pinned[2];
+        return QSIM_OK;
+    });
 }
 
 int qsim_probs(const qsim_state *s, uint64_t qubit_mask, double *out, size_t out_len)
 {
-    if (s == nullptr || out == nullptr)
-        return fail(QSIM_EINVAL, "NULL argument");
-    const uint64_t full = (1ull << s->M) - 1;
-    if (qubit_mask & ~full)
-        return fail(QSIM_EINVAL, "mask has bits at or above qubit %d", s->M);
-    const int m = __builtin_popcountll(qubit_mask);
-    if (out_len != (1ull << m))
-        return fail(QSIM_EINVAL, "out_len %zu != 2^%d", out_len, m);
-    qsim_state *ms = const_cast<qsim_state *>(s);
-    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
-    const size_t out_bytes = out_len * sizeof(double);
-    if (qubit_mask == full) {
-        int rc = ensure_stage(ms, out_bytes);
-        if (rc != QSIM_OK)
-            return rc;
-        Timed t(ms, 2, 0);
-        HIP_TRY(s->dtype == QSIM_C64
-                    ? launch_probs_full<float>((const cplx<float> *)s->psi, s->M,
-                                               (double *)s->d_stage, s->stream)
-                    : launch_probs_full<double>((const cplx<double> *)s->psi, s->M,
-                                                (double *)s->d_stage, s->stream),
-                "probs launch");
-        t.done();
-    } else {
-        const uint64_t plen = probs_marginal_partial_len(s->M, qubit_mask);
-        const size_t out_off = (plen * sizeof(double) + 255) & ~(size_t)255;
-        int rc = ensure_stage(ms, out_off + out_bytes);
-        if (rc != QSIM_OK)
-            return rc;
-        double *partial = (double *)s->d_stage;
-        double *dout = (double *)((char *)s->d_stage + out_off);
-        Timed t(ms, 2, 0);
-        HIP_TRY(s->dtype == QSIM_C64
-                    ? launch_probs_marginal<float>((const cplx<float> *)s->psi, s->M, qubit_mask,
-                                                   partial, plen, dout, s->stream)
-                    : launch_probs_marginal<double>((const cplx<double> *)s->psi, s->M,
-                                                    qubit_mask, partial, plen, dout, s->stream),
-                "marginal launch");
-        t.done();
-        HIP_TRY(hipMemcpyAsync(out, dout, out_bytes, hipMemcpyDeviceToHost, s->stream),
+    return guarded(__func__, [&]() -> int {
+        if (s == nullptr || out == nullptr)
+            return fail(QSIM_EINVAL, "NULL argument");
+        const uint64_t full = (1ull << s->M) - 1;
+        if (qubit_mask & ~full)
+            return fail(QSIM_EINVAL, "mask has bits at or above qubit %d", s->M);
+        const int m = __builtin_popcountll(qubit_mask);
+        if (out_len != (1ull << m))
+            return fail(QSIM_EINVAL, "out_len %zu != 2^%d", out_len, m);
+        qsim_state *ms = const_cast<qsim_state *>(s);
+        HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+        const size_t out_bytes = out_len * sizeof(double);
+        if (qubit_mask == full) {
+            int rc = ensure_stage(ms, out_bytes);
+            if (rc != QSIM_OK)
+                return rc;
+            Timed t(ms, 2, 0);
+            HIP_TRY(s->dtype == QSIM_C64
+                        ? launch_probs_full<float>((const cplx<float> *)s->psi, s->M,
+                                                   (double *)s->d_stage, s->stream)
+                        : launch_probs_full<double>((const cplx<double> *)s->psi, s->M,
+                                                    (double *)s->d_stage, s->stream),
+                    "probs launch");
+            t.done();
+        } else {
+            const uint64_t plen = probs_marginal_partial_len(s->M, qubit_mask);
+            const size_t out_off = (plen * sizeof(double) + 255) & ~(size_t)255;
+            int rc = ensure_stage(ms, out_off + out_bytes);
+            if (rc != QSIM_OK)
+                return rc;
+            double *partial = (double *)s->d_stage;
+            double *dout = (double *)((char *)s->d_stage + out_off);
+            Timed t(ms, 2, 0);
+            HIP_TRY(s->dtype == QSIM_C64
+                        ? launch_probs_marginal<float>((const cplx<float> *)s->psi, s->M, qubit_mask,
+                                                       partial, plen, dout, s->stream)
+                        : launch_probs_marginal<double>((const cplx<double> *)s->psi, s->M,
+                                                        qubit_mask, partial, plen, dout, s->stream),
+                    "marginal launch");
+            t.done();
+            HIP_TRY(hipMemcpyAsync(out, dout, out_bytes, hipMemcpyDeviceToHost, s->stream),
+                    "probs copy");
+            HIP_TRY(hipStreamSynchronize(s->stream), "probs sync");
+            return QSIM_OK;
+        }
+        HIP_TRY(hipMemcpyAsync(out, s->d_stage, out_bytes, hipMemcpyDeviceToHost, s->stream),
                 "probs copy");
         HIP_TRY(hipStreamSynchronize(s->stream), "probs sync");
         return QSIM_OK;
-    }
-    HIP_TRY(hipMemcpyAsync(out, s->d_stage, out_bytes, hipMemcpyDeviceToHost, s->stream),
-            "probs copy");
-    HIP_TRY(hipStreamSynchronize(s->stream), "probs sync");
-    return QSIM_OK;
+    });
 }
 
 int qsim_get_amplitudes(const qsim_state *s, uint64_t offset, uint64_t count, double *out)
 {
-    if (s == nullptr || (out == nullptr && count > 0))
-        return fail(QSIM_EINVAL, "NULL argument");
-    const uint64_t n = 1ull << s->M;
-    if (offset > n || count > n - offset)
-        return fail(QSIM_ERANGE, "range [%llu, +%llu) outside 2^%d amplitudes",
-                    (unsigned long long)offset, (unsigned long long)count, s->M);
-    qsim_state *ms = const_cast<qsim_state *>(s);
-    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
-    const uint64_t chunk = std::min<uint64_t>(count, 1ull << 22);
-    if (count == 0)
+    return guarded(__func__, [&]() -> int {
+        if (s == nullptr || (out == nullptr && count > 0))
+            return fail(QSIM_EINVAL, "NULL argument");
+        const uint64_t n = 1ull << s->M;
+        if (offset > n || count > n - offset)
+            return fail(QSIM_ERANGE, "range [%llu, +%llu) outside 2^%d amplitudes",
+                        (unsigned long long)offset, (unsigned long long)count, s->M);
+        qsim_state *ms = const_cast<qsim_state *>(s);
+        HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+        const uint64_t chunk = std::min<uint64_t>(count, 1ull << 22);
+        if (count == 0)
+            return QSIM_OK;
+        int rc = ensure_stage(ms, chunk * 16);
+        if (rc != QSIM_OK)
+            return rc;
+        for (uint64_t done = 0; done < count; done += chunk) {
+            const uint64_t c = std::min(chunk, count - done);
+            HIP_TRY(s->dtype == QSIM_C64
+                        ? launch_to_f64<float>((const cplx<float> *)s->psi + offset + done, c,
+                                               (double *)s->d_stage, s->stream)
+                        : launch_to_f64<double>((const cplx<double> *)s->psi + offset + done, c,
+                                                (double *)s->d_stage, s->stream),
+                    "convert launch");
+            HIP_TRY(hipMemcpyAsync(out + 2 * done, s->d_stage, c * 16, hipMemcpyDeviceToHost,
+                                   s->stream), "amplitude copy");
+            HIP_TRY(hipStreamSynchronize(s->stream), "amplitude sync");
+        }
         return QSIM_OK;
-    int rc = ensure_stage(ms, chunk * 16);
-    if (rc != QSIM_OK)
-        return rc;
-    for (uint64_t done = 0; done < count; done += chunk) {
-        const uint64_t c = std::min(chunk, count - done);
-        HIP_TRY(s->dtype == QSIM_C64
-                    ? launch_to_f64<float>((const cplx<float> *)s->psi + offset + done, c,
-                                           (double *)s->d_stage, s->stream)
-                    : launch_to_f64<double>((const cplx<double> *)s->psi + offset + done, c,
-                                            (double *)s->d_stage, s->stream),
-                "convert launch");
-        HIP_TRY(hipMemcpyAsync(out + 2 * done, s->d_stage, c * 16, hipMemcpyDeviceToHost,
-                               s->stream), "amplitude copy");
-        HIP_TRY(hipStreamSynchronize(s->stream), "amplitude sync");
-    }
-    return QSIM_OK;
+    });
 }
 
 int qsim_set_amplitudes(qsim_state *s, uint64_t offset, uint64_t count, const double *in)
 {
-    if (s == nullptr || (in == nullptr && count > 0))
-        return fail(QSIM_EINVAL, "NULL argument");
-    const uint64_t n = 1ull << s->M;
-    if (offset > n || count > n - offset)
-        return fail(QSIM_ERANGE, "range outside the register");
-    for (uint64_t i = 0; i < 2 * count; ++i)
-        if (!std::isfinite(in[i]))
-            return fail(QSIM_EINVAL, "non-finite input at %llu", (unsigned long long)i);
-    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
-    if (count == 0)
+    return guarded(__func__, [&]() -> int {
+        if (s == nullptr || (in == nullptr && count > 0))
+            return fail(QSIM_EINVAL, "NULL argument");
+        const uint64_t n = 1ull << s->M;
+        if (offset > n || count > n - offset)
+            return fail(QSIM_ERANGE, "range outside the register");
+        for (uint64_t i = 0; i < 2 * count; ++i)
+            if (!std::isfinite(in[i]))
+                return fail(QSIM_EINVAL, "non-finite input at %llu", (unsigned long long)i);
+        HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+        if (count == 0)
+            return QSIM_OK;
+        const uint64_t chunk = std::min<uint64_t>(count, 1ull << 22);
+        int rc = ensure_stage(s, chunk * 16);
+        if (rc != QSIM_OK)
+            return rc;
+        for (uint64_t done = 0; done < count; done += chunk) {
+            const uint64_t c = std::min(chunk, count - done);
+            HIP_TRY(hipMemcpyAsync(s->d_stage, in + 2 * done, c * 16, hipMemcpyHostToDevice,
+                                   s->stream), "amplitude copy");
+            HIP_TRY(s->dtype == QSIM_C64
+                        ? launch_from_f64<float>((const double *)s->d_stage, c,
+                                                 (cplx<float> *)s->psi + offset + done, s->stream)
+                        : launch_from_f64<double>((const double *)s->d_stage, c,
+                                                  (cplx<double> *)s->psi + offset + done, s->stream),
+                    "convert launch");
+            HIP_TRY(hipStreamSynchronize(s->stream), "amplitude sync");
+        }
         return QSIM_OK;
-    const uint64_t chunk = std::min<uint64_t>(count, 1ull << 22);
-    int rc = ensure_stage(s, chunk * 16);
-    if (rc != QSIM_OK)
-        return rc;
-    for (uint64_t done = 0; done < count; done += chunk) {
-        const uint64_t c = std::min(chunk, count - done);
-        HIP_TRY(hipMemcpyAsync(s->d_stage, in + 2 * done, c * 16, hipMemcpyHostToDevice,
-                               s->stream), "amplitude copy");
-        HIP_TRY(s->dtype == QSIM_C64
-                    ? launch_from_f64<float>((const double *)s->d_stage, c,
-                                             (cplx<float> *)s->psi + offset + done, s->stream)
-                    : launch_from_f64<double>((const double *)s->d_stage, c,
-                                              (cplx<double> *)s->psi + offset + done, s->stream),
-                "convert launch");
-        HIP_TRY(hipStreamSynchronize(s->stream), "amplitude sync");
-    }
-    return QSIM_OK;
+    });
 }
 
 int qsim_plan(int num_qubits, int dtype, const qsim_options *opt, const qsim_gate *gates,
@@ -1472,108 +1500,116 @@ int qsim_plan(int num_qubits, int dtype, const qsim_options *opt, const qsim_gat
               size_t out_cap, size_t *n_passes, size_t *n_ops, uint32_t *op_order,
               size_t order_cap)
 {
-    qsim_options o{};
-    if (opt)
-        o = *opt;
-    qsim_state st;
-    int rc = configure(&st, num_qubits, dtype, o);
-    if (rc != QSIM_OK)
-        return rc;
-    rc = validate_gates(&st, gates, n_gates);
-    if (rc != QSIM_OK)
-        return rc;
-    if (em) {
-        if (!error_model_valid(*em))
-            return fail(QSIM_EINVAL, "bad error model");
-        st.em = *em;
-        st.armed = true;
-    }
-    st.step = step0;
-    std::vector<Op> stream;
-    lower_circuit(&st, gates, n_gates, stream);
-    std::vector<PassPlan> plan;
-    std::vector<uint32_t> order;
-    schedule(&st, stream, order, plan);
-    std::vector<Op> ops(order.size());
-    for (size_t i = 0; i < order.size(); ++i)
-        ops[i] = stream[order[i]];
-    if (n_passes)
-        *n_passes = plan.size();
-    if (n_ops)
-        *n_ops = ops.size();
-    if (op_order)
-        for (size_t i = 0; i < order.size() && i < order_cap; ++i)
-            op_order[i] = order[i];
-    for (size_t i = 0; i < plan.size(); ++i) {
-        qsim_pass_info info{};
-        info.fused = plan[i].fused ? 1u : 0u;
-        info.first_op = (uint32_t)plan[i].first;
-        info.n_ops = (uint32_t)plan[i].count;
-        info.norm_after = plan[i].norm_after ? 1u : 0u;
-        for (size_t j = plan[i].first; j < plan[i].first + plan[i].count; ++j)
-            info.flops += op_flops(ops[j], num_qubits);
-        if (plan[i].fused) {
-            char why[160];
-            int G = 0;
-            bool ok;
-            if (dtype == QSIM_C64) {
-                TileArgs<float> A;
-                build_tile_args<float>(&st, ops, plan[i], A, G);
-                ok = tile_args_consistent<float>(A, G, ops, plan[i], why, sizeof(why));
-                info.n_groups = A.ngroups;
-                info.tile_mask = A.smask;
-            } else {
-                TileArgs<double> A;
-                build_tile_args<double>(&st, ops, plan[i], A, G);
-                ok = tile_args_consistent<double>(A, G, ops, plan[i], why, sizeof(why));
-                info.n_groups = A.ngroups;
-                info.tile_mask = A.smask;
-            }
-            if (!ok)
-                return fail(QSIM_EDEVICE, "internal: pass %zu inconsistent: %s", i, why);
+    return guarded(__func__, [&]() -> int {
+        qsim_options o{};
+        if (opt)
+            o = *opt;
+        qsim_state st;
+        int rc = configure(&st, num_qubits, dtype, o);
+        if (rc != QSIM_OK)
+            return rc;
+        rc = validate_gates(&st, gates, n_gates);
+        if (rc != QSIM_OK)
+            return rc;
+        if (em) {
+            if (!error_model_valid(*em))
+                return fail(QSIM_EINVAL, "bad error model");
+            st.em = *em;
+            st.armed = true;
         }
-        if (out && i < out_cap)
-            out[i] = info;
-    }
-    return QSIM_OK;
+        st.step = step0;
+        std::vector<Op> stream;
+        lower_circuit(&st, gates, n_gates, stream);
+        std::vector<PassPlan> plan;
+        std::vector<uint32_t> order;
+        schedule(&st, stream, order, plan);
+        std::vector<Op> ops(order.size());
+        for (size_t i = 0; i < order.size(); ++i)
+            ops[i] = stream[order[i]];
+        if (n_passes)
+            *n_passes = plan.size();
+        if (n_ops)
+            *n_ops = ops.size();
+        if (op_order)
+            for (size_t i = 0; i < order.size() && i < order_cap; ++i)
+                op_order[i] = order[i];
+        for (size_t i = 0; i < plan.size(); ++i) {
+            qsim_pass_info info{};
+            info.fused = plan[i].fused ? 1u : 0u;
+            info.first_op = (uint32_t)plan[i].first;
+            info.n_ops = (uint32_t)plan[i].count;
+            info.norm_after = plan[i].norm_after ? 1u : 0u;
+            for (size_t j = plan[i].first; j < plan[i].first + plan[i].count; ++j)
+                info.flops += op_flops(ops[j], num_qubits);
+            if (plan[i].fused) {
+                char why[160];
+                int G = 0;
+                bool ok;
+                if (dtype == QSIM_C64) {
+                    TileArgs<float> A;
+                    build_tile_args<float>(&st, ops, plan[i], A, G);
+                    ok = tile_args_consistent<float>(A, G, ops, plan[i], why, sizeof(why));
+                    info.n_groups = A.ngroups;
+                    info.tile_mask = A.smask;
+                } else {
+                    TileArgs<double> A;
+                    build_tile_args<double>(&st, ops, plan[i], A, G);
+                    ok = tile_args_consistent<double>(A, G, ops, plan[i], why, sizeof(why));
+                    info.n_groups = A.ngroups;
+                    info.tile_mask = A.smask;
+                }
+                if (!ok)
+                    return fail(QSIM_EDEVICE, "internal: pass %zu inconsistent: %s", i, why);
+            }
+            if (out && i < out_cap)
+                out[i] = info;
+        }
+        return QSIM_OK;
+    });
 }
 
 int qsim_info(const qsim_state *s, int *num_qubits, int *dtype, uint64_t *step, void **device_ptr,
               size_t *bytes)
 {
-    if (s == nullptr)
-        return fail(QSIM_EINVAL, "state is NULL");
-    if (num_qubits) *num_qubits = s->M;
-    if (dtype) *dtype = s->dtype;
-    if (step) *step = s->step;
-    if (device_ptr) *device_ptr = s->psi;
-    if (bytes) *bytes = s->bytes;
-    return QSIM_OK;
+    return guarded(__func__, [&]() -> int {
+        if (s == nullptr)
+            return fail(QSIM_EINVAL, "state is NULL");
+        if (num_qubits) *num_qubits = s->M;
+        if (dtype) *dtype = s->dtype;
+        if (step) *step = s->step;
+        if (device_ptr) *device_ptr = s->psi;
+        if (bytes) *bytes = s->bytes;
+        return QSIM_OK;
+    });
 }
 
 int qsim_profile(qsim_state *s, int enable)
 {
-    if (s == nullptr)
-        return fail(QSIM_EINVAL, "state is NULL");
-    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
-    int rc = flush_timings(s);
-    if (rc != QSIM_OK)
-        return rc;
-    s->stats = qsim_stats{};
-    s->profiling = enable != 0;
-    return QSIM_OK;
+    return guarded(__func__, [&]() -> int {
+        if (s == nullptr)
+            return fail(QSIM_EINVAL, "state is NULL");
+        HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+        int rc = flush_timings(s);
+        if (rc != QSIM_OK)
+            return rc;
+        s->stats = qsim_stats{};
+        s->profiling = enable != 0;
+        return QSIM_OK;
+    });
 }
 
 int qsim_get_stats(qsim_state *s, qsim_stats *out)
 {
-    if (s == nullptr || out == nullptr)
-        return fail(QSIM_EINVAL, "NULL argument");
-    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
-    int rc = flush_timings(s);
-    if (rc != QSIM_OK)
-        return rc;
-    *out = s->stats;
-    return QSIM_OK;
+    return guarded(__func__, [&]() -> int {
+        if (s == nullptr || out == nullptr)
+            return fail(QSIM_EINVAL, "NULL argument");
+        HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+        int rc = flush_timings(s);
+        if (rc != QSIM_OK)
+            return rc;
+        *out = s->stats;
+        return QSIM_OK;
+    });
 }
 
 }  // extern "C"

@@ -4,13 +4,33 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <exception>
+#include <new>
 
 #include "qsim.h"
 
 namespace qsim {
 
 // Record a message for qsim_last_error (per thread) and return `code`.
+// Allocates nothing.
 int set_error(int code, const char *fmt, ...);
+
+// Run the body of an exported function so that no C++ exception crosses the
+// C-ABI: host memory exhaustion becomes QSIM_ENOMEM, any other exception
+// QSIM_EDEVICE, each with a message naming the function.
+template <typename F>
+int guarded(const char *fn, F &&body) noexcept
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return set_error(QSIM_ENOMEM, "%s: host memory exhausted", fn);
+    } catch (const std::exception &e) {
+        return set_error(QSIM_EDEVICE, "%s: internal error: %s", fn, e.what());
+    } catch (...) {
+        return set_error(QSIM_EDEVICE, "%s: internal error", fn);
+    }
+}
 
 // Kind, arity and qubit checks of one gate on an M-qubit register; `why`
 // receives the reason when the gate is rejected.

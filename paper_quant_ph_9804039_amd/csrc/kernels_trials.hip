@@ -94,24 +94,38 @@ __device__ void gate_matrix(uint32_t kind, double theta, double eps, uint32_t &t
 //           the target's position among the group qubits, 15 when it is not
 //           one; forms 0-3 as in TrialOp, and for an uncontrolled Hadamard 4
 //           = the butterfly (a + b, a - b) and 5 = (b - a, a + b), each plus
-//           i t on the diagonal with t = u[0].im (the scale dropped);
+//           i t on the diagonal with t = u[0].im;
+//   scale = the real factor the butterfly forms leave out (the Hadamard's
+//           h cos(eps/2)), 1 for every other form: the group multiplies its
+//           quantum by the product of its gates' scales at its end, so the
+//           register keeps its true norm;
 //   regs  = rm | rv << 8 | rz << 16: controls on group qubits and the values
 //           they need, and phase flips on group qubits, over the register
 //           index;
 //   lm, lv: controls on the other qubits and their values, over the thread's
 //           base index; zmask: all phase flips after the gate.
-// A diagonal is kept as diag(1, q) with u[3] = q (the trial's global phase
-// does not change its fidelity).
+// A diagonal is kept as diag(1, q) with u[3] = q: its d0 has modulus one, so
+// dropping it changes the trial's state by a global phase only, which the
+// fidelity does not see.
 template <typename R>
 struct TrialGateOp {
     cplx<R> u[4];
+    R scale;
     uint32_t meta;
     uint32_t regs;
     uint32_t lm;
     uint32_t lv;
     uint32_t zmask;
-    uint32_t pad[3];
+    uint32_t pad[sizeof(R) == 4 ? 2 : 1];
 };
+static_assert(sizeof(TrialGateOp<float>) == 64 && sizeof(TrialGateOp<double>) == 96,
+              "trial gate records: 64 / 96 bytes");
+
+// A butterfly leaves out at most this much growth per gate: (B + i t I) with
+// |t| <= 1 has operator norm sqrt(2 + t^2) <= sqrt(3), and the host closes a
+// register group after kMaxGroupButterflies uncontrolled Hadamards, so a
+// quantum grows by at most 3^16 before its group's end restores the scale.
+constexpr double kMaxButterflyT = 1.0;
 
 // Build the trial's operations for gates [c0, c0 + cn) of the circuit in
 // LDS (ops), drawing the chunk's flips (one Philox block per (step, qubit))
@@ -649,15 +663,21 @@ __global__ void __launch_bounds__(kPrepThreads) k_trial_prep(const TrialLaunch L
             const bool real_diag = u[1] == 0.0 && u[7] == 0.0;
             const bool zero_diag = u[0] == 0.0 && u[6] == 0.0;
             uint32_t form = !real_off ? 3u : real_diag ? 0u : zero_diag ? 2u : 1u;
-            // an uncontrolled Hadamard, perturbed or not, is h (B + i t) with
-            // B = [[1, 1], [1, -1]], or [[-1, 1], [1, 1]] after X U X; the
-            // real scale h does not change the trial's fidelity, so the pair
-            // update is the butterfly B plus i t on the diagonal (t in u[0].im)
+            op.scale = R(1);
+            // an uncontrolled Hadamard, perturbed or not, is hb (B + i t) with
+            // B = [[1, 1], [1, -1]], or [[-1, 1], [1, 1]] after X U X, and
+            // hb = h cos(eps/2): the pair update is the butterfly B plus i t
+            // on the diagonal (t in u[0].im), and hb goes to the record's
+            // scale, which the group applies at its end.  Only while |t| <= 1
+            // (|eps| below about 1.23), which bounds the growth inside a
+            // group; beyond that the gate keeps its full coefficients.
             const double hb = u[2];
             if (type == kOpMat && gd.cmask == 0 && real_off && hb != 0.0 && u[4] == hb &&
-                u[1] == u[7] && ((u[0] == hb && u[6] == -hb) || (u[0] == -hb && u[6] == hb))) {
+                u[1] == u[7] && ((u[0] == hb && u[6] == -hb) || (u[0] == -hb && u[6] == hb)) &&
+                fabs(u[1]) <= kMaxButterflyT * fabs(hb)) {
                 form = u[0] == hb ? 4u : 5u;
                 op.u[0].im = (R)(u[1] / hb);
+                op.scale = (R)hb;
             }
             // positions relative to the gate's group
             const uint32_t w = gword[g];
@@ -682,7 +702,8 @@ __global__ void __launch_bounds__(kPrepThreads) k_trial_prep(const TrialLaunch L
             // phase flips follow this step's bit flips; Z_q on the true
             // register is Z_q on the stored one up to a global sign
             op.zmask = zm & ~gmask;
-            op.pad[0] = op.pad[1] = op.pad[2] = 0;
+            for (uint32_t &pw : op.pad)
+                pw = 0;
             ops[g] = op;
         }
         X ^= scan[kPrepThreads - 1];
@@ -753,17 +774,25 @@ __global__ void __launch_bounds__(T) k_trials_groups(const TrialLaunch L, uint64
             // than its inputs, and the second writes them back
             cplx<R> F = {R(1), R(0)};
             bool useF = false;
+            R S = R(1);  // scales the butterflies of the group left out
             const uint32_t end = first + count;
             for (uint32_t g = first; g < end; g += 2) {
                 trial_apply<R, G>(tops[g], j0, x, F, useF);
+                S *= tops[g].scale;
                 if (g + 1 >= end)
                     break;
                 trial_apply<R, G>(tops[g + 1], j0, x, F, useF);
+                S *= tops[g + 1].scale;
             }
             if (useF) {
+                F = {F.re * S, F.im * S};
 #pragma unroll
                 for (int r = 0; r < (1 << G); ++r)
                     x[r] = cmul(x[r], F);
+            } else if (S != R(1)) {
+#pragma unroll
+                for (int r = 0; r < (1 << G); ++r)
+                    x[r] = {x[r].re * S, x[r].im * S};
             }
         }
         // fidelity against the error-free register, reading psi(i) = s(i ^ X)
@@ -805,16 +834,9 @@ hipError_t launch_t(const TrialLaunch &L, hipStream_t st)
 {
     const size_t lds = trial_lds_bytes((int)L.M, (int)sizeof(cplx<R>));
     auto fn = k_trials<R, T>;
-    static size_t lds_allowed = 65536;  // per instantiation
-    if (lds > lds_allowed) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return e;
-        }
-        lds_allowed = lds;
-    }
+    const hipError_t e = kernel_allow_lds(reinterpret_cast<const void *>(fn), lds);
+    if (e != hipSuccess)
+        return e;
     const uint64_t grid = L.n_trials < (uint64_t)L.grid ? L.n_trials : (uint64_t)L.grid;
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(T), lds, st, L.gates, L.ngates, L.M,
                        L.sigma, L.p_bit, L.p_phase, L.seed, L.trial0, L.n_trials,
@@ -827,16 +849,9 @@ hipError_t launch_g(const TrialLaunch &L, hipStream_t st)
 {
     const size_t lds = trial_group_lds<R>((int)L.M);
     auto fn = k_trials_groups<R, G, T>;
-    static size_t lds_allowed = 65536;  // per instantiation
-    if (lds > lds_allowed) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return e;
-        }
-        lds_allowed = lds;
-    }
+    const hipError_t ea = kernel_allow_lds(reinterpret_cast<const void *>(fn), lds);
+    if (ea != hipSuccess)
+        return ea;
     TrialGateOp<R> *ops = reinterpret_cast<TrialGateOp<R> *>(L.prep_ops);
     for (uint64_t t0 = 0; t0 < L.n_trials; t0 += L.prep_batch) {
         const uint64_t nt = std::min<uint64_t>(L.prep_batch, L.n_trials - t0);
@@ -872,22 +887,8 @@ hipError_t launch_groups(const TrialLaunch &L, hipStream_t st)
 template <typename R, int G, int T>
 int grid_g(int M)
 {
-    const size_t lds = trial_group_lds<R>(M);
-    auto fn = k_trials_groups<R, G, T>;
-    if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds) != hipSuccess) {
-        (void)hipGetLastError();
-        return 0;
-    }
-    int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, T, lds) != hipSuccess ||
-        hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-        (void)hipGetLastError();
-        return 0;
-    }
-    return per_cu * cus;
+    return kernel_resident_blocks(reinterpret_cast<const void *>(k_trials_groups<R, G, T>), T,
+                                  trial_group_lds<R>(M));
 }
 
 template <typename R, int G>
@@ -937,22 +938,8 @@ size_t trial_gate_op_bytes(int elem_bytes)
 template <typename R, int T>
 int grid_t(int M)
 {
-    const size_t lds = trial_lds_bytes(M, (int)sizeof(cplx<R>));
-    auto fn = k_trials<R, T>;
-    if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds) != hipSuccess) {
-        (void)hipGetLastError();
-        return 0;
-    }
-    int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, T, lds) != hipSuccess ||
-        hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-        (void)hipGetLastError();
-        return 0;
-    }
-    return per_cu * cus;
+    return kernel_resident_blocks(reinterpret_cast<const void *>(k_trials<R, T>), T,
+                                  trial_lds_bytes(M, (int)sizeof(cplx<R>)));
 }
 
 int trial_grid(int variant, int M, int elem_bytes)

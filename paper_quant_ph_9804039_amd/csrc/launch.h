@@ -8,6 +8,16 @@
 
 namespace qsim {
 
+// Raise `fn`'s dynamic-LDS allowance on the current device to at least
+// `lds` bytes (allowances only grow; sizes up to 64 KiB need none).
+// Thread-safe.
+hipError_t kernel_allow_lds(const void *fn, size_t lds);
+// Workgroups of `threads` threads and `lds` bytes of dynamic LDS that are
+// resident on the current device at once (per-CU occupancy times CUs),
+// computed once per (kernel, device, shape); 0 if the kernel cannot run so.
+// Thread-safe.
+int kernel_resident_blocks(const void *fn, int threads, size_t lds);
+
 // |k>: zero the vector and set amplitude k to 1 (a fill kernel, not a memset,
 // so it can sit in captured graphs).
 template <typename R>
@@ -88,6 +98,10 @@ struct TrialLaunch {
     uint64_t prep_batch;
 };
 size_t trial_gate_op_bytes(int elem_bytes);
+// Register groups of the register-group variants hold at most this many
+// uncontrolled Hadamards (gates the preparation kernel may turn into
+// butterflies whose scale the group restores at its end).
+constexpr uint32_t kMaxGroupButterflies = 32;
 // LDS of the sweep variants (register plus a chunk of built gates).
 size_t trial_lds_bytes(int M, int elem_bytes);
 // Group qubits of a register-group variant (0 for the LDS-sweep variants).

@@ -149,151 +149,153 @@ int admit(Slot &sl, const qsim_request &r, char *base)
 extern "C" int qsim_serve(const qsim_request *reqs, size_t n, const qsim_serve_options *opt,
                           qsim_result *out)
 {
-    if (n > 0 && (reqs == nullptr || out == nullptr))
-        return set_error(QSIM_EINVAL, "NULL argument");
-    qsim_serve_options o{};
-    if (opt)
-        o = *opt;
-    const int nslots = o.max_slots == 0 ? 8 : o.max_slots;
-    if (nslots < 1 || nslots > 64)
-        return set_error(QSIM_EINVAL, "max_slots %d outside [1, 64]", o.max_slots);
-    int max_m = 1;
-    char why[160];
-    for (size_t i = 0; i < n; ++i) {
-        const qsim_request &r = reqs[i];
-        if (r.num_qubits < 1 || r.num_qubits > QSIM_MAX_QUBITS)
-            return set_error(QSIM_EINVAL, "request %zu: num_qubits %d", i, r.num_qubits);
-        if (r.dtype != QSIM_C64 && r.dtype != QSIM_C128)
-            return set_error(QSIM_EINVAL, "request %zu: dtype %d", i, r.dtype);
-        if (!(r.arrival_s >= 0.0) || !std::isfinite(r.arrival_s))
-            return set_error(QSIM_EINVAL, "request %zu: arrival time", i);
-        if (!error_model_valid(r.errors))
-            return set_error(QSIM_EINVAL, "request %zu: error model", i);
-        if (r.n_gates > 0 && r.gates == nullptr)
-            return set_error(QSIM_EINVAL, "request %zu: gates is NULL", i);
-        for (size_t k = 0; k < r.n_gates; ++k)
-            if (!gate_valid(r.gates[k], r.num_qubits, why, sizeof(why)))
-                return set_error(QSIM_EINVAL, "request %zu gate %zu: %s", i, k, why);
-        max_m = std::max(max_m, r.num_qubits);
-    }
-    for (size_t i = 0; i < n; ++i)
-        out[i] = qsim_result{0.0, -1.0, -1.0, QSIM_OK, -1};
-    if (n == 0)
-        return QSIM_OK;
+    return guarded(__func__, [&]() -> int {
+        if (n > 0 && (reqs == nullptr || out == nullptr))
+            return set_error(QSIM_EINVAL, "NULL argument");
+        qsim_serve_options o{};
+        if (opt)
+            o = *opt;
+        const int nslots = o.max_slots == 0 ? 8 : o.max_slots;
+        if (nslots < 1 || nslots > 64)
+            return set_error(QSIM_EINVAL, "max_slots %d outside [1, 64]", o.max_slots);
+        int max_m = 1;
+        char why[160];
+        for (size_t i = 0; i < n; ++i) {
+            const qsim_request &r = reqs[i];
+            if (r.num_qubits < 1 || r.num_qubits > QSIM_MAX_QUBITS)
+                return set_error(QSIM_EINVAL, "request %zu: num_qubits %d", i, r.num_qubits);
+            if (r.dtype != QSIM_C64 && r.dtype != QSIM_C128)
+                return set_error(QSIM_EINVAL, "request %zu: dtype %d", i, r.dtype);
+            if (!(r.arrival_s >= 0.0) || !std::isfinite(r.arrival_s))
+                return set_error(QSIM_EINVAL, "request %zu: arrival time", i);
+            if (!error_model_valid(r.errors))
+                return set_error(QSIM_EINVAL, "request %zu: error model", i);
+            if (r.n_gates > 0 && r.gates == nullptr)
+                return set_error(QSIM_EINVAL, "request %zu: gates is NULL", i);
+            for (size_t k = 0; k < r.n_gates; ++k)
+                if (!gate_valid(r.gates[k], r.num_qubits, why, sizeof(why)))
+                    return set_error(QSIM_EINVAL, "request %zu gate %zu: %s", i, k, why);
+            max_m = std::max(max_m, r.num_qubits);
+        }
+        for (size_t i = 0; i < n; ++i)
+            out[i] = qsim_result{0.0, -1.0, -1.0, QSIM_OK, -1};
+        if (n == 0)
+            return QSIM_OK;
 
-    hipError_t e = hipSetDevice(o.device);
-    if (e != hipSuccess)
-        return hip_err(e, "hipSetDevice");
-    size_t budget = o.hbm_budget;
-    if (budget == 0) {
-        size_t fr = 0, tot = 0;
-        if ((e = hipMemGetInfo(&fr, &tot)) != hipSuccess)
-            return hip_err(e, "hipMemGetInfo");
-        budget = std::min((size_t)64 << 30, (size_t)(0.8 * (double)fr));
-    }
-    Loop L;
-    if ((e = hipMalloc(&L.arena_mem, budget)) != hipSuccess)
-        return hip_err(e, "arena");
-    Arena arena(budget);
-    L.slots.resize(nslots);
-    for (Slot &sl : L.slots) {
-        if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess)
-            return hip_err(e, "slot stream");
-        if ((e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess)
-            return hip_err(e, "slot event");
-        if ((e = hipHostMalloc((void **)&sl.result, 4 * sizeof(double), hipHostMallocDefault)) !=
-            hipSuccess)
-            return hip_err(e, "slot result");
-        int rc = slot_state_create(o.device, sl.stream, max_m, &sl.ideal);
-        if (rc == QSIM_OK)
-            rc = slot_state_create(o.device, sl.stream, max_m, &sl.noisy);
-        if (rc != QSIM_OK)
-            return rc;
-    }
+        hipError_t e = hipSetDevice(o.device);
+        if (e != hipSuccess)
+            return hip_err(e, "hipSetDevice");
+        size_t budget = o.hbm_budget;
+        if (budget == 0) {
+            size_t fr = 0, tot = 0;
+            if ((e = hipMemGetInfo(&fr, &tot)) != hipSuccess)
+                return hip_err(e, "hipMemGetInfo");
+            budget = std::min((size_t)64 << 30, (size_t)(0.8 * (double)fr));
+        }
+        Loop L;
+        if ((e = hipMalloc(&L.arena_mem, budget)) != hipSuccess)
+            return hip_err(e, "arena");
+        Arena arena(budget);
+        L.slots.resize(nslots);
+        for (Slot &sl : L.slots) {
+            if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess)
+                return hip_err(e, "slot stream");
+            if ((e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess)
+                return hip_err(e, "slot event");
+            if ((e = hipHostMalloc((void **)&sl.result, 4 * sizeof(double), hipHostMallocDefault)) !=
+                hipSuccess)
+                return hip_err(e, "slot result");
+            int rc = slot_state_create(o.device, sl.stream, max_m, &sl.ideal);
+            if (rc == QSIM_OK)
+                rc = slot_state_create(o.device, sl.stream, max_m, &sl.noisy);
+            if (rc != QSIM_OK)
+                return rc;
+        }
 
-    std::vector<size_t> order(n);
-    for (size_t i = 0; i < n; ++i)
-        order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t a, size_t b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
-    std::deque<size_t> waiting;
-    size_t next = 0, finished = 0;
-    char *base = reinterpret_cast<char *>(L.arena_mem);
-    const auto t0 = std::chrono::steady_clock::now();
-    auto now = [&] {
-        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    };
-    while (finished < n) {
-        bool progress = false;
-        const double t = now();
-        while (next < n && reqs[order[next]].arrival_s <= t) {
-            const size_t i = order[next++];
-            if (footprint(reqs[i]) > budget) {
-                out[i].status = QSIM_ENOMEM;
-                out[i].done_s = t;
+        std::vector<size_t> order(n);
+        for (size_t i = 0; i < n; ++i)
+            order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](size_t a, size_t b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
+        std::deque<size_t> waiting;
+        size_t next = 0, finished = 0;
+        char *base = reinterpret_cast<char *>(L.arena_mem);
+        const auto t0 = std::chrono::steady_clock::now();
+        auto now = [&] {
+            return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        };
+        while (finished < n) {
+            bool progress = false;
+            const double t = now();
+            while (next < n && reqs[order[next]].arrival_s <= t) {
+                const size_t i = order[next++];
+                if (footprint(reqs[i]) > budget) {
+                    out[i].status = QSIM_ENOMEM;
+                    out[i].done_s = t;
+                    ++finished;
+                } else {
+                    waiting.push_back(i);
+                }
+                progress = true;
+            }
+            // completions
+            for (size_t si = 0; si < L.slots.size(); ++si) {
+                Slot &sl = L.slots[si];
+                if (!sl.busy)
+                    continue;
+                e = hipEventQuery(sl.done);
+                if (e == hipErrorNotReady)
+                    continue;
+                qsim_result &res = out[sl.req];
+                if (e == hipSuccess) {
+                    const double *v = sl.result;
+                    res.fidelity = (v[0] * v[0] + v[1] * v[1]) / (v[2] * v[3]);
+                } else {
+                    res.status = hip_err(e, "request work");
+                }
+                res.done_s = now();
+                arena.release(sl.off, sl.bytes);
+                sl.busy = false;
                 ++finished;
-            } else {
-                waiting.push_back(i);
+                progress = true;
             }
-            progress = true;
-        }
-        // completions
-        for (size_t si = 0; si < L.slots.size(); ++si) {
-            Slot &sl = L.slots[si];
-            if (!sl.busy)
-                continue;
-            e = hipEventQuery(sl.done);
-            if (e == hipErrorNotReady)
-                continue;
-            qsim_result &res = out[sl.req];
-            if (e == hipSuccess) {
-                const double *v = sl.result;
-                res.fidelity = (v[0] * v[0] + v[1] * v[1]) / (v[2] * v[3]);
-            } else {
-                res.status = hip_err(e, "request work");
-            }
-            res.done_s = now();
-            arena.release(sl.off, sl.bytes);
-            sl.busy = false;
-            ++finished;
-            progress = true;
-        }
-        // admissions, in arrival order
-        for (auto it = waiting.begin(); it != waiting.end();) {
-            auto free_slot = std::find_if(L.slots.begin(), L.slots.end(),
-                                          [](const Slot &s) { return !s.busy; });
-            if (free_slot == L.slots.end())
-                break;
-            const size_t i = *it;
-            size_t off = 0;
-            const size_t bytes = footprint(reqs[i]);
-            if (!arena.alloc(bytes, off)) {
-                if (o.strict_fifo)
+            // admissions, in arrival order
+            for (auto it = waiting.begin(); it != waiting.end();) {
+                auto free_slot = std::find_if(L.slots.begin(), L.slots.end(),
+                                              [](const Slot &s) { return !s.busy; });
+                if (free_slot == L.slots.end())
                     break;
-                ++it;
-                continue;
+                const size_t i = *it;
+                size_t off = 0;
+                const size_t bytes = footprint(reqs[i]);
+                if (!arena.alloc(bytes, off)) {
+                    if (o.strict_fifo)
+                        break;
+                    ++it;
+                    continue;
+                }
+                Slot &sl = *free_slot;
+                sl.off = off;
+                sl.bytes = bytes;
+                sl.req = i;
+                out[i].admit_s = now();
+                out[i].slot = (int)(free_slot - L.slots.begin());
+                const int rc = admit(sl, reqs[i], base);
+                if (rc != QSIM_OK) {
+                    (void)hipStreamSynchronize(sl.stream);
+                    arena.release(off, bytes);
+                    out[i].status = rc;
+                    out[i].done_s = now();
+                    ++finished;
+                } else {
+                    sl.busy = true;
+                }
+                it = waiting.erase(it);
+                progress = true;
             }
-            Slot &sl = *free_slot;
-            sl.off = off;
-            sl.bytes = bytes;
-            sl.req = i;
-            out[i].admit_s = now();
-            out[i].slot = (int)(free_slot - L.slots.begin());
-            const int rc = admit(sl, reqs[i], base);
-            if (rc != QSIM_OK) {
-                (void)hipStreamSynchronize(sl.stream);
-                arena.release(off, bytes);
-                out[i].status = rc;
-                out[i].done_s = now();
-                ++finished;
-            } else {
-                sl.busy = true;
-            }
-            it = waiting.erase(it);
-            progress = true;
+            if (!progress)
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
-        if (!progress)
-            std::this_thread::sleep_for(std::chrono::microseconds(20));
-    }
-    return QSIM_OK;
+        return QSIM_OK;
+    });
 }

@@ -557,40 +557,19 @@ hipError_t launch_gt(const TileArgs<R> &A, hipStream_t st)
     if (A.k != (uint32_t)G + (uint32_t)__builtin_ctz(T))
         return hipErrorInvalidValue;
     const size_t lds = A.ngroups > 1 ? tile_lds_bytes((int)A.k, (int)sizeof(cplx<R>)) : 0;
-    auto fn = k_tile<R, G, T>;
+    const void *fn = reinterpret_cast<const void *>(k_tile<R, G, T>);
     // more than 64 KiB of dynamic LDS must be allowed per kernel first
-    static size_t lds_allowed = 65536;  // per instantiation
-    if (lds > lds_allowed) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return e;
-        }
-        lds_allowed = lds;
-    }
-    // persistent grid: as many workgroups as fit on the chip at once
-    static int occ_cache[2] = {0, 0};  // [uses LDS], per instantiation
-    int &occ = occ_cache[lds > 0 ? 1 : 0];
-    if (occ == 0) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, T, lds) != hipSuccess ||
-            per_cu < 1) {
-            (void)hipGetLastError();
-            per_cu = 1;
-        }
-        int dev = 0, cus = 0;
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            cus < 1) {
-            (void)hipGetLastError();
-            cus = 256;
-        }
-        occ = per_cu * cus;
-    }
+    hipError_t e = kernel_allow_lds(fn, lds);
+    if (e != hipSuccess)
+        return e;
+    // persistent grid: as many workgroups as fit on the chip at once (one
+    // per CU of the 256 if the occupancy query fails)
+    int occ = kernel_resident_blocks(fn, T, lds);
+    if (occ <= 0)
+        occ = 256;
     const uint64_t tiles = 1ull << (A.M - A.k);
     const uint64_t grid = tiles < (uint64_t)occ ? tiles : (uint64_t)occ;
-    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(T), lds, st, A);
+    hipLaunchKernelGGL((k_tile<R, G, T>), dim3((unsigned)grid), dim3(T), lds, st, A);
     return hipGetLastError();
 }
 

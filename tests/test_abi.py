@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -90,3 +91,33 @@ def test_argument_errors_without_gpu(libpath):
     assert L.qsim_run_trials(g.ctypes.data, 1, 40, 0, ctypes.byref(em), 4,
                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == q.QSIM_EINVAL
     assert L.qsim_destroy(None) == q.QSIM_OK
+
+
+def test_host_memory_exhaustion_is_a_status_not_an_abort(libpath, tmp_path):
+    """No C++ exception crosses the C-ABI: qsim_plan on a circuit whose
+    lowered operation stream cannot fit the address space it is given (every
+    qubit flips after every gate) returns QSIM_ENOMEM with a message instead
+    of terminating the process.  Run in a child process under RLIMIT_AS."""
+    script = tmp_path / "enomem.py"
+    script.write_text(f'''
+import ctypes, resource, sys
+sys.path.insert(0, {ROOT!r})
+import numpy as np
+import circuitgen as cg
+import paper_quant_ph_9804039_amd as q
+L = q.lib()
+gates = cg.random_circuit(30, 200000, 1)
+em = q.qsim_error_model(0.0, 1.0, 1.0, 1, 0)
+vm = [int(l.split()[1]) for l in open("/proc/self/status") if l.startswith("VmSize")][0] * 1024
+soft, hard = resource.getrlimit(resource.RLIMIT_AS)
+resource.setrlimit(resource.RLIMIT_AS, (vm + (512 << 20), hard))
+npass, nops = ctypes.c_size_t(), ctypes.c_size_t()
+rc = L.qsim_plan(30, 0, None, gates.ctypes.data, len(gates), ctypes.byref(em), 0, None, 0,
+                 ctypes.byref(npass), ctypes.byref(nops), None, 0)
+print(rc, L.qsim_last_error().decode())
+''')
+    r = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    rc, msg = r.stdout.split(" ", 1)
+    assert int(rc) == q.QSIM_ENOMEM, r.stdout
+    assert "qsim_plan" in msg and "memory" in msg

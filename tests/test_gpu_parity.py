@@ -121,10 +121,13 @@ def _check_vs_oracle(M, gates, dtype, mode, em=None, tol_amp=1e-12, tol_f=1e-12,
         F_ref = oracle.fidelity(ideal_ref, noisy_ref, M)
         assert abs(F - F_ref) <= tol_f, (F, F_ref)
         for st, ref in ((ideal, ideal_ref), (noisy, noisy_ref)):
+            # raw amplitudes: a wrong global scale (a dropped factor, a
+            # missed renormalisation) fails here, not only a wrong direction
             a = st.amplitudes()
             r = oracle_c(ref)
-            a_n = a / np.linalg.norm(a)
-            assert np.max(np.abs(a_n - r)) <= tol_amp
+            assert np.all(np.isfinite(a))
+            assert np.max(np.abs(a - r)) <= tol_amp
+            assert abs(np.vdot(a, a).real - np.vdot(r, r).real) <= 10 * tol_amp
             cplx = np.vdot(r, a)
             assert 1.0 - abs(cplx) ** 2 / np.vdot(a, a).real <= max(tol_f, 1e-15)
     return F, F_ref

@@ -43,19 +43,23 @@ def test_trial_equals_per_register_path():
 
 def test_config3_shape_m14_c64_sample_against_oracle():
     """M=14, 500 gates, sigma=1e-3, p=1e-4 (complex64 state, FP64 reductions):
-    a sample of the batch checked trial by trial against the FP64 oracle."""
-    M, G = 14, 500
+    the first 64 trials of a 4096-trial batch checked one by one against the
+    FP64 oracle, every trial finite and in [0, 1]."""
+    M, G, K = 14, 500, 64
     gates = cg.random_circuit(M, G, 14)
     em = oracle.Errors(sigma=1e-3, p_bitflip=1e-4, p_phaseflip=1e-4, seed=1014, trial=0)
+    print("config3 M=14 c64 4096 trials, 64 against the oracle", flush=True)
     got = q.qsim_run_trials(gates, M, q.QSIM_C64, em.sigma, em.p_bitflip, em.p_phaseflip,
-                            em.seed, 0, 512)
-    want = oracle.run_trials(gates, M, em, 8)
-    assert np.max(np.abs(got[:8] - want)) < 1e-6
+                            em.seed, 0, 4096)
+    want = oracle.run_trials(gates, M, em, K)
+    assert np.all(np.isfinite(got))
+    assert np.max(np.abs(got[:K] - want)) < 1e-6
     assert np.all((got >= -1e-6) & (got <= 1 + 1e-6))
     # trials without any flip keep F close to 1 - O(G sigma^2)
-    flip_free = [t for t in range(8)
+    flip_free = [t for t in range(K)
                  if all(oracle.flip_events(oracle.Errors(1e-3, 1e-4, 1e-4, 1014, t), s, qb) == 0
                         for s in range(G) for qb in range(M))]
+    assert flip_free
     for t in flip_free:
         assert got[t] > 0.99
 
@@ -132,3 +136,44 @@ def test_workspace_kept_between_calls_changes_no_result():
     assert np.array_equal(b1, b2)
     want = oracle.run_trials(gb, 13, oracle.Errors(0.02, 1e-3, 1e-3, 9, 0), 2)
     assert np.max(np.abs(b2[:2] - want)) < 1e-12
+
+
+@pytest.mark.parametrize("variant", [2, 3])
+@pytest.mark.parametrize("M,dtype,tol", [(14, q.QSIM_C64, 1e-6), (13, q.QSIM_C128, 1e-12)])
+def test_register_group_variants_long_circuits(monkeypatch, variant, M, dtype, tol):
+    """2000-gate circuits through the register-group variants (the ones the
+    autotuner picks for config 3).  Regression: their butterfly form of the
+    uncontrolled Hadamard once dropped its real scale, so the squared norm
+    doubled with every H; a float32 emulation of this generator
+    (random_circuit(14, 2000, 14)) overflowed at gate 1061, after 267 H, and
+    complex128 overflowed near 2000 H.  The scale is now restored at the end
+    of every register group, so the trials stay finite and match the
+    oracle."""
+    print(f"long trials variant={variant} M={M} dtype={dtype}", flush=True)
+    monkeypatch.setenv("QSIM_TRIAL_VARIANT", str(variant))
+    gates = cg.random_circuit(M, 2000, M)
+    em = oracle.Errors(sigma=1e-3, p_bitflip=1e-4, p_phaseflip=1e-4, seed=2000 + M, trial=0)
+    want = oracle.run_trials(gates, M, em, 16)
+    got = q.qsim_run_trials(gates, M, dtype, em.sigma, em.p_bitflip, em.p_phaseflip, em.seed,
+                            em.trial, 16)
+    assert np.all(np.isfinite(got))
+    assert np.max(np.abs(got - want)) < tol, np.max(np.abs(got - want))
+
+
+@pytest.mark.parametrize("variant", [2, 3])
+@pytest.mark.parametrize("sigma", [0.05, 2.0])
+@pytest.mark.parametrize("dtype,tol", [(q.QSIM_C64, 1e-6), (q.QSIM_C128, 1e-12)])
+def test_register_group_variants_hadamard_heavy(monkeypatch, variant, sigma, dtype, tol):
+    """Hadamard-only circuits (every gate a butterfly candidate, so groups are
+    cut by the 32-butterfly bound alone) and, at sigma = 2, angle errors large
+    enough that many Hadamards keep their full coefficients instead (|t| > 1)."""
+    M = 11
+    print(f"H-heavy trials variant={variant} sigma={sigma} dtype={dtype}", flush=True)
+    monkeypatch.setenv("QSIM_TRIAL_VARIANT", str(variant))
+    gates = cg.random_circuit(M, 600, 611, kinds=(cg.H,))
+    em = oracle.Errors(sigma=sigma, p_bitflip=1e-3, p_phaseflip=1e-3, seed=611, trial=5)
+    want = oracle.run_trials(gates, M, em, 16)
+    got = q.qsim_run_trials(gates, M, dtype, em.sigma, em.p_bitflip, em.p_phaseflip, em.seed,
+                            em.trial, 16)
+    assert np.all(np.isfinite(got))
+    assert np.max(np.abs(got - want)) < tol, np.max(np.abs(got - want))

@@ -130,3 +130,47 @@ def test_pass_flops_count_each_operations_2x2(gate, sigma, per_amp, controls):
     passes, nops = q.qsim_plan(M, q.QSIM_C64, cg.gates_from_list([gate]), sigma=sigma, seed=3)
     assert nops == 1 and len(passes) == 1
     assert passes[0]["flops"] == per_amp * 2.0 ** (M - controls)
+
+
+@pytest.mark.parametrize("group_bits", [4, 5])
+@pytest.mark.parametrize("M,G,seed,kinds", [
+    (14, 2000, 14, None),
+    (13, 2000, 13, None),
+    (11, 600, 5, (cg.H,)),
+    (12, 400, 6, (cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT, cg.TOFFOLI)),
+])
+def test_trial_group_schedule(group_bits, M, G, seed, kinds):
+    """The Monte Carlo register-group schedule: groups cover the circuit in
+    order, each group's non-diagonal targets lie on its group_bits qubits, and
+    no group holds more than 32 uncontrolled Hadamards -- the bound the
+    kernel's per-group rescale relies on.  Regression: before the rescale the
+    butterfly form dropped each Hadamard's real scale, so the squared norm
+    doubled with every uncontrolled H (a float32 emulation of the config-3
+    generator, random_circuit(14, 2000, 14), overflowed at gate 1061)."""
+    if M - group_bits < 6 or M - group_bits > 10:
+        pytest.skip("register-group kernels need 6 <= M - G <= 10")
+    gates = cg.random_circuit(M, G, seed, **({"kinds": kinds} if kinds else {}))
+    rows = q.qsim_trial_plan(gates, M, group_bits)
+    nxt = 0
+    for first, count, mask, nbf in rows:
+        assert first == nxt and count >= 1
+        assert bin(int(mask)).count("1") == group_bits and int(mask) < (1 << M)
+        seg = gates[first:first + count]
+        for g in seg:
+            if g["kind"] not in (cg.RZ, cg.Z):
+                assert (int(mask) >> int(g["target"])) & 1
+        want_bf = sum(1 for g in seg if g["kind"] == cg.H and g["ctrl0"] < 0)
+        assert nbf == want_bf and nbf <= 32
+        nxt += count
+    assert nxt == G
+    if kinds == (cg.H,):
+        # Hadamard-only circuits are cut by the butterfly bound alone
+        assert len(rows) >= G // 32
+
+
+def test_trial_plan_rejects_bad_input():
+    g = cg.random_circuit(12, 10, 1)
+    for M, gb in ((12, 3), (12, 6), (9, 4), (16, 5)):
+        with pytest.raises(q.QsimError) as e:
+            q.qsim_trial_plan(g, M, gb)
+        assert e.value.code == q.QSIM_EINVAL
