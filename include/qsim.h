@@ -183,6 +183,26 @@ int qsim_fidelity(const qsim_state *a, const qsim_state *b, double *out_F);
 /* out = {re <a|b>, im <a|b>, <a|a>, <b|b>} in FP64 (same rules as above). */
 int qsim_overlap(const qsim_state *a, const qsim_state *b, double out[4]);
 
+/* The overlap of qsim_overlap for callers that cannot allocate memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the two registers are caller-owned device memory, not states.
+ * a and b hold 2^num_qubits interleaved (re, im) amplitudes of dtype_a and
+ * dtype_b (QSIM_C64 or QSIM_C128), 16-byte aligned, on `device`; they are
+ * only read.  The work is queued on hip_stream (NULL: the null stream) and
+ * the call waits for it; out (host) receives {re <a|b>, im <a|b>, <a|a>,
+ * <b|b>} in FP64, bit-identical to qsim_overlap on the same amplitudes (same
+ * kernels, same fixed reduction order).  No memory is allocated, host or
+ * device: the reduction's per-block partials and results sit in a static
+ * device array of 32.1 KiB per device (4 x 1024 partials + results, enough
+ * for every num_qubits in 1..QSIM_MAX_QUBITS), held until the process ends.
+ * Calls on one device share that array: they are serialised inside the
+ * process, and calls on one device from several processes must not overlap.
+ * EINVAL for num_qubits outside [1, QSIM_MAX_QUBITS], a bad dtype or device,
+ * a NULL, misaligned or non-device pointer, or an allocation smaller than the
+ * register; EDEVICE if a HIP call fails. */
+int qsim_overlap_noalloc(const void *a, int dtype_a, const void *b, int dtype_b, int num_qubits,
+                         int device, void *hip_stream, double out[4]);
+
 /* Squared norm <s|s> in FP64. */
 int qsim_norm(const qsim_state *s, double *out);
 

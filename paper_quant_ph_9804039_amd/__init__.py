@@ -33,7 +33,7 @@ EXPORTED = [
     "qsim_inject_errors", "qsim_fidelity", "qsim_overlap", "qsim_norm", "qsim_probs",
     "qsim_get_amplitudes", "qsim_set_amplitudes", "qsim_run_trials", "qsim_synchronize",
     "qsim_info", "qsim_profile", "qsim_get_stats", "qsim_last_error", "qsim_plan", "qsim_serve",
-    "qsim_trial_plan",
+    "qsim_trial_plan", "qsim_overlap_noalloc",
 ]
 
 
@@ -135,6 +135,8 @@ def lib() -> ctypes.CDLL:
                        ctypes.POINTER(qsim_result)],
         "qsim_trial_plan": [vp, sz, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint32),
                             sz, ctypes.POINTER(sz)],
+        "qsim_overlap_noalloc": [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 vp, dp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -210,6 +212,16 @@ def qsim_fidelity(a, b) -> float:
 def qsim_overlap(a, b):
     out = np.zeros(4)
     _check(lib().qsim_overlap(a, b, _dp(out)))
+    return complex(out[0], out[1]), float(out[2]), float(out[3])
+
+
+def qsim_overlap_noalloc(ptr_a: int, dtype_a: int, ptr_b: int, dtype_b: int, num_qubits: int,
+                         device: int = 0, hip_stream=None):
+    """Overlap of two caller-owned device registers (raw device addresses);
+    allocates nothing.  Returns (<a|b>, <a|a>, <b|b>)."""
+    out = np.zeros(4)
+    _check(lib().qsim_overlap_noalloc(ptr_a, dtype_a, ptr_b, dtype_b, num_qubits, device,
+                                      hip_stream, _dp(out)))
     return complex(out[0], out[1]), float(out[2]), float(out[3])
 
 
