@@ -18,9 +18,11 @@ from __future__ import annotations
 
 import numpy as np
 
-H, RZ, X, CNOT, TOFFOLI, Z = 0, 1, 2, 3, 4, 5
-KIND_NAMES = {H: "H", RZ: "RZ", X: "X", CNOT: "CNOT", TOFFOLI: "TOFFOLI", Z: "Z"}
-ARITY = {H: 1, RZ: 1, X: 1, CNOT: 2, TOFFOLI: 3, Z: 1}
+H, RZ, X, CNOT, TOFFOLI, Z, CPHASE = 0, 1, 2, 3, 4, 5, 6
+KIND_NAMES = {H: "H", RZ: "RZ", X: "X", CNOT: "CNOT", TOFFOLI: "TOFFOLI", Z: "Z",
+              CPHASE: "CPHASE"}
+ARITY = {H: 1, RZ: 1, X: 1, CNOT: 2, TOFFOLI: 3, Z: 1, CPHASE: 2}
+ANGLED = (RZ, CPHASE)  # kinds whose theta is an angle
 
 GATE_DTYPE = np.dtype(
     [("kind", "<u4"), ("target", "<i4"), ("ctrl0", "<i4"), ("ctrl1", "<i4"), ("theta", "<f8")],
@@ -48,10 +50,11 @@ def random_circuit(num_qubits: int, num_gates: int, seed: int,
     """Uniform random circuit over ``kinds`` on distinct random qubits.
 
     Per gate: kind uniform over ``kinds``; qubits drawn without replacement,
-    the last one is the target and the rest are controls; RZ angle uniform on
-    [0, 2*pi).  With ``top_bias`` > 0 the target is, with that probability,
-    uniform over the top ``top_count`` qubits, otherwise uniform over all
-    qubits; controls are then uniform over the remaining qubits.
+    the last one is the target and the rest are controls; RZ and CPHASE
+    angles uniform on [0, 2*pi).  With ``top_bias`` > 0 the target is, with
+    that probability, uniform over the top ``top_count`` qubits, otherwise
+    uniform over all qubits; controls are then uniform over the remaining
+    qubits.
     """
     M = int(num_qubits)
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -72,7 +75,7 @@ def random_circuit(num_qubits: int, num_gates: int, seed: int,
         else:
             qs = [int(q) for q in rng.choice(M, ar, replace=False)]
             tgt, ctrls = qs[-1], qs[:-1]
-        theta = float(rng.uniform(0.0, 2.0 * np.pi)) if kind == RZ else 0.0
+        theta = float(rng.uniform(0.0, 2.0 * np.pi)) if kind in ANGLED else 0.0
         c0 = ctrls[0] if len(ctrls) > 0 else -1
         c1 = ctrls[1] if len(ctrls) > 1 else -1
         out[g] = (kind, tgt, c0, c1, theta)
@@ -119,6 +122,31 @@ def modexp15_circuit(a_qubits: int = 4, qubit_map=None) -> np.ndarray:
         if len(qm) != a_qubits + 4 or len(set(qm)) != len(qm):
             raise ValueError("qubit_map needs a_qubits + 4 distinct qubits")
         items = [(it[0],) + tuple(qm[x] for x in it[1:]) for it in items]
+    return gates_from_list(items)
+
+
+def qft_circuit(qubits, swaps: bool = True) -> np.ndarray:
+    """Quantum Fourier transform (the quantum FFT of Sec. 2.2) on the listed
+    qubits, qubits[0] the least significant bit of the register value x:
+    |x> -> 2^(-n/2) sum_y e^(2 pi i x y / 2^n) |y>.
+
+    Most significant bit first: H on it, then a controlled phase of
+    pi / 2^(j-k) from each lower bit k; the result then holds y with its bits
+    in reverse order, which the closing swaps (three CNOTs each) undo.  Gates:
+    H, CPHASE and CNOT."""
+    q = [int(x) for x in qubits]
+    if len(set(q)) != len(q):
+        raise ValueError("qft_circuit needs distinct qubits")
+    n = len(q)
+    items = []
+    for j in range(n - 1, -1, -1):
+        items.append((H, q[j]))
+        for k in range(j - 1, -1, -1):
+            items.append((CPHASE, q[j], q[k], -1, np.pi / float(1 << (j - k))))
+    if swaps:
+        for i in range(n // 2):
+            a, b = q[i], q[n - 1 - i]
+            items.extend([(CNOT, a, b), (CNOT, b, a), (CNOT, a, b)])
     return gates_from_list(items)
 
 

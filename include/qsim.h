@@ -62,18 +62,24 @@ typedef struct qsim_state qsim_state; /* opaque, owned by the library */
 
 typedef enum { QSIM_C64 = 0, QSIM_C128 = 1 } qsim_dtype;
 
-/* Gate kinds.  Arity: H, RZ, X, Z act on `target` alone; CNOT adds ctrl0;
- * TOFFOLI adds ctrl0 and ctrl1.  Unused controls are -1. */
+/* Gate kinds.  Arity: H, RZ, X, Z act on `target` alone; CNOT and CPHASE
+ * add ctrl0; TOFFOLI adds ctrl0 and ctrl1.  Unused controls are -1.
+ * CPHASE(theta) is the conditional phase rotation of the quantum FFT
+ * (Sec. 2.2): diag(1, e^{i theta}) on the target where ctrl0 is 1, i.e. the
+ * amplitudes with both bits set gain e^{i theta}; an angle error makes it
+ * CPHASE(theta + eps), as Rz(theta) becomes Rz(theta + eps). */
 typedef enum {
     QSIM_H = 0,
     QSIM_RZ = 1,
     QSIM_X = 2,
     QSIM_CNOT = 3,
     QSIM_TOFFOLI = 4,
-    QSIM_Z = 5
+    QSIM_Z = 5,
+    QSIM_CPHASE = 6
 } qsim_kind;
 
-/* One gate, 24 bytes.  theta is the Rz angle in radians (ignored otherwise). */
+/* One gate, 24 bytes.  theta is the Rz or CPHASE angle in radians (ignored
+ * otherwise). */
 typedef struct {
     uint32_t kind;
     int32_t target;
@@ -153,8 +159,9 @@ int qsim_reset(qsim_state *s, uint64_t basis_index);
 int qsim_apply_circuit(qsim_state *s, const qsim_gate *gates, size_t n_gates);
 
 /* Apply the exact inverse of gates[0..n_gates): the gates in reverse order,
- * Rz(t) as Rz(-t), the others as themselves, with no errors and without
- * advancing the step counter.  After a noisy run of a circuit, this leaves
+ * Rz(t) as Rz(-t), CPHASE(t) as CPHASE(-t), the others as themselves, with
+ * no errors and without advancing the step counter.  After a noisy run of a
+ * circuit, this leaves
  * <0|U_ideal^dagger U_noisy|0> in amplitude 0 (the echo form of the fidelity,
  * for registers too large to hold two states). */
 int qsim_apply_inverse(qsim_state *s, const qsim_gate *gates, size_t n_gates);
@@ -230,7 +237,9 @@ int qsim_set_amplitudes(qsim_state *s, uint64_t offset, uint64_t count, const do
  * value qsim_fidelity gives for two registers run that way).  All trials
  * run in one persistent launch, one register per workgroup, which needs the
  * register to fit the workgroup's LDS (num_qubits <= 14 for QSIM_C64,
- * <= 13 for QSIM_C128); EINVAL beyond that.  Synchronous.  Runs on `device`
+ * <= 13 for QSIM_C128); EINVAL beyond that, and for CPHASE gates (the
+ * trial kernels take the gate set H, Rz, X, CNOT, Toffoli, Z).  Synchronous.
+ * Runs on `device`
  * 0 unless QSIM_DEVICE is set in the environment.  The kernel variant (one
  * LDS sweep per gate, or the register held in registers with 4 or 5 group
  * qubits) is picked by timing each on one round of trials, once per

@@ -9,7 +9,8 @@ index bit 2^q, so the leftmost factor is qubit M-1) with a projector onto
 It deliberately shares nothing with the pair-loop oracle in qsim_oracle.c:
 the perturbed one-qubit gates are built here with scipy's matrix exponential,
 i * expm(-i (pi + eps)/2 A) for a gate whose own rotation axis is A
-(A = H, X or Z) and expm(-i (theta + eps)/2 Z) for Rz; the random draws come
+(A = H, X or Z), expm(-i (theta + eps)/2 Z) for Rz and expm(i (theta + eps)
+|1><1|) for the controlled phase; the random draws come
 from numpy's own Philox4x64-10 generator.  The draw recipe (key = (seed,
 trial), counter = (step, qubit, stream, 0), Box-Muller on the high halves of
 words 0 and 1 for the angle, high halves below floor(p 2^32) for the flips)
@@ -20,7 +21,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg
 
-from circuitgen import CNOT, H, RZ, TOFFOLI, X, Z
+from circuitgen import CNOT, CPHASE, H, RZ, TOFFOLI, X, Z
 
 I2 = np.eye(2, dtype=complex)
 PAULI_X = np.array([[0, 1], [1, 0]], dtype=complex)
@@ -32,6 +33,8 @@ PROJ1 = np.array([[0, 0], [0, 1]], dtype=complex)
 def one_qubit_matrix(kind: int, theta: float, eps: float) -> np.ndarray:
     if kind == RZ:
         return scipy.linalg.expm(-0.5j * (theta + eps) * PAULI_Z)
+    if kind == CPHASE:  # e^{i phi} on |1> of the target (the control is a projector)
+        return scipy.linalg.expm(1j * (theta + eps) * PROJ1)
     axis = {H: HADAMARD, X: PAULI_X, CNOT: PAULI_X, TOFFOLI: PAULI_X, Z: PAULI_Z}[kind]
     if eps == 0.0:
         return axis.copy()

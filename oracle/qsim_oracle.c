@@ -32,9 +32,12 @@
  *     amplitudes a2 and a3 swap, as in Fig. 2;
  *   - the superposition gate is the Hadamard, H = sqrt(1/2) [[1,1],[1,-1]];
  *   - Rz(theta) = diag(e^{-i theta/2}, e^{+i theta/2});
+ *   - the controlled phase CPHASE(theta) multiplies the amplitudes whose
+ *     control and target bits are both 1 by e^{i theta}: diag(1, e^{i theta})
+ *     on the target where the control is set;
  *   - one angle error eps = sigma * z per gate (z standard normal); H, X,
  *     CNOT, Toffoli and Z are then i * R_n(pi + eps), with n the gate's own
- *     rotation axis, and Rz(theta) becomes Rz(theta + eps); with eps == 0
+ *     rotation axis, and Rz(theta) and CPHASE(theta) take theta + eps; with eps == 0
  *     every gate is its textbook form and X/CNOT/Toffoli/Z are exact swaps
  *     and sign flips;
  *   - decoherence after every gate: for each qubit q = 0..M-1 in turn, a
@@ -57,7 +60,7 @@
 #include <omp.h>
 #endif
 
-enum { OQ_H = 0, OQ_RZ = 1, OQ_X = 2, OQ_CNOT = 3, OQ_TOFFOLI = 4, OQ_Z = 5 };
+enum { OQ_H = 0, OQ_RZ = 1, OQ_X = 2, OQ_CNOT = 3, OQ_TOFFOLI = 4, OQ_Z = 5, OQ_CPHASE = 6 };
 
 typedef struct {
     uint32_t kind;
@@ -194,6 +197,12 @@ int oq_gate_matrix(uint32_t kind, double theta, double eps, double u[8])
         u[4] = c;
         u[7] = -s;
         return 0;
+    case OQ_CPHASE: { /* diag(1, e^{i phi}); the control is applied by the caller */
+        double phi = theta + eps;
+        u[0] = 1.0;
+        u[6] = cos(phi); u[7] = sin(phi);
+        return 0;
+    }
     case OQ_Z:
         if (eps == 0.0) {
             u[0] = 1.0; u[6] = -1.0;
@@ -275,8 +284,8 @@ void oq_init(double *psi, int M, uint64_t k)
 
 static int gate_valid(const oq_gate *g, int M)
 {
-    int need = (g->kind == OQ_CNOT) ? 1 : (g->kind == OQ_TOFFOLI) ? 2 : 0;
-    if (g->kind > OQ_Z)
+    int need = (g->kind == OQ_CNOT || g->kind == OQ_CPHASE) ? 1 : (g->kind == OQ_TOFFOLI) ? 2 : 0;
+    if (g->kind > OQ_CPHASE)
         return 0;
     if (g->target < 0 || g->target >= M)
         return 0;

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libqsim.so")
 
 QSIM_OK, QSIM_EINVAL, QSIM_ENOMEM, QSIM_EDEVICE, QSIM_ERANGE = 0, -1, -2, -3, -4
 QSIM_C64, QSIM_C128 = 0, 1
-QSIM_H, QSIM_RZ, QSIM_X, QSIM_CNOT, QSIM_TOFFOLI, QSIM_Z = 0, 1, 2, 3, 4, 5
+QSIM_H, QSIM_RZ, QSIM_X, QSIM_CNOT, QSIM_TOFFOLI, QSIM_Z, QSIM_CPHASE = 0, 1, 2, 3, 4, 5, 6
 QSIM_MAX_QUBITS = 34
 
 EXPORTED = [

@@ -201,7 +201,7 @@ bool qsim::gate_valid(const qsim_gate &g, int M, char *why, size_t n)
     int need;
     switch (g.kind) {
     case QSIM_H: case QSIM_RZ: case QSIM_X: case QSIM_Z: need = 0; break;
-    case QSIM_CNOT: need = 1; break;
+    case QSIM_CNOT: case QSIM_CPHASE: need = 1; break;
     case QSIM_TOFFOLI: need = 2; break;
     default: snprintf(why, n, "unknown gate kind %u", g.kind); return false;
     }
@@ -246,7 +246,7 @@ namespace {
 
 // The 2x2 of a gate with angle error eps (FP64).  eps == 0 gives the textbook
 // gate; otherwise the gate is i R_n(pi + eps) about its own axis n, and Rz(t)
-// is Rz(t + eps).
+// and CPHASE(t) take t + eps.
 Op lower_gate(const qsim_gate &g, double eps, bool inverse)
 {
     Op op{};
@@ -277,6 +277,14 @@ Op lower_gate(const qsim_gate &g, double eps, bool inverse)
         const double phi = (inverse ? -g.theta : g.theta) + eps;
         const double cp = std::cos(0.5 * phi), sp = std::sin(0.5 * phi);
         set(0, cp, -sp); set(3, cp, sp);
+        break;
+    }
+    case QSIM_CPHASE: {
+        // diag(1, e^{i phi}) on the target where the control is set (the
+        // conditional rotations of the quantum FFT, Sec. 2.2)
+        op.type = kOpDiag;
+        const double phi = (inverse ? -g.theta : g.theta) + eps;
+        set(0, 1, 0); set(3, std::cos(phi), std::sin(phi));
         break;
     }
     case QSIM_X: case QSIM_CNOT: case QSIM_TOFFOLI:

@@ -296,9 +296,13 @@ extern "C" int qsim_run_trials(const qsim_gate *gates, size_t n, int num_qubits,
         if (n > (size_t)UINT32_MAX)
             return set_error(QSIM_EINVAL, "too many gates");
         char why[160];
-        for (size_t k = 0; k < n; ++k)
+        for (size_t k = 0; k < n; ++k) {
             if (!gate_valid(gates[k], num_qubits, why, sizeof(why)))
                 return set_error(QSIM_EINVAL, "gate %zu: %s", k, why);
+            if (gates[k].kind == QSIM_CPHASE)
+                return set_error(QSIM_EINVAL, "gate %zu: the trial kernels do not take "
+                                 "controlled phases", k);
+        }
         if (n_trials == 0)
             return QSIM_OK;
 
@@ -479,9 +483,13 @@ extern "C" int qsim_trial_plan(const qsim_gate *gates, size_t n, int num_qubits,
         if (n > (size_t)UINT32_MAX)
             return set_error(QSIM_EINVAL, "too many gates");
         char why[160];
-        for (size_t k = 0; k < n; ++k)
+        for (size_t k = 0; k < n; ++k) {
             if (!gate_valid(gates[k], num_qubits, why, sizeof(why)))
                 return set_error(QSIM_EINVAL, "gate %zu: %s", k, why);
+            if (gates[k].kind == QSIM_CPHASE)
+                return set_error(QSIM_EINVAL, "gate %zu: the trial kernels do not take "
+                                 "controlled phases", k);
+        }
         std::vector<uint32_t> sched;
         uint32_t nchunks = 0, ngroups = 0;
         group_schedule(gates, n, num_qubits, group_bits, sched, nchunks, ngroups);

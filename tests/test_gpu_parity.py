@@ -378,3 +378,102 @@ def test_fig4_modexp_circuit(mode, dtype, tol):
     _check_vs_oracle(M, gates, dtype, mode, em,
                      tol_amp=1e-12 if dtype == q.QSIM_C128 else 2e-5,
                      tol_f=1e-12 if dtype == q.QSIM_C128 else 1e-6)
+
+
+# ------------------------------------------- controlled phase and quantum FFT
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dtype", [q.QSIM_C64, q.QSIM_C128])
+def test_cphase_on_basis_states(mode, dtype):
+    """CPHASE(theta) multiplies |k> by e^{i theta} exactly when its control
+    and target bits are both set; other basis states stay bit-identical."""
+    M, theta = 11, 0.8125
+    rng = np.random.default_rng(66)
+    tol = 1e-15 if dtype == q.QSIM_C128 else 1e-7
+    with state(M, dtype, exec_mode=mode) as s:
+        for _ in range(6):
+            c, t = (int(x) for x in rng.choice(M, 2, replace=False))
+            g = cg.gates_from_list([(cg.CPHASE, t, c, -1, theta)])
+            for k in rng.choice(1 << M, 12, replace=False):
+                k = int(k)
+                s.reset(k)
+                s.apply(g)
+                a = s.amplitudes()
+                both = (k >> c) & 1 and (k >> t) & 1
+                want = complex(np.cos(theta), np.sin(theta)) if both else 1.0
+                assert abs(a[k] - want) <= tol and np.count_nonzero(a) == 1, (c, t, k)
+                if not both:
+                    assert a[k] == 1.0
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dtype,tol_amp,tol_f", [(q.QSIM_C128, 1e-12, 1e-12),
+                                                 (q.QSIM_C64, 2e-5, 1e-6)])
+def test_circuits_with_cphase_vs_oracle(mode, dtype, tol_amp, tol_f):
+    """Random circuits over H, Rz, CNOT, Toffoli and CPHASE with angle errors
+    and flips, several tiles and a ragged tail of operations."""
+    M = 15
+    gates = cg.random_circuit(M, 260, 915, kinds=(cg.H, cg.RZ, cg.CNOT, cg.TOFFOLI, cg.CPHASE))
+    em = oracle.Errors(sigma=2e-3, p_bitflip=2e-4, p_phaseflip=2e-4, seed=9150, trial=1)
+    _check_vs_oracle(M, gates, dtype, mode, em, tol_amp=tol_amp, tol_f=tol_f)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dtype", [q.QSIM_C64, q.QSIM_C128])
+def test_qft_closed_form(mode, dtype):
+    """Sec. 2.2's quantum FFT on n = 12 of M = 14 qubits (the listed qubits
+    scattered over the register): |x> goes to 2^(-n/2) sum_y e^(2 pi i x y /
+    2^n) |y>, checked element by element for a few x."""
+    M, n = 14, 12
+    qs = [0, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12, 13]
+    gates = cg.qft_circuit(qs)
+    tol = 1e-13 if dtype == q.QSIM_C128 else 1e-6
+    y = np.arange(1 << n)
+    idx = np.zeros(1 << n, dtype=np.int64)
+    for i, qb in enumerate(qs):
+        idx |= ((y >> i) & 1) << qb
+    with state(M, dtype, exec_mode=mode) as s:
+        for x in (0, 1, 5, 1234, (1 << n) - 1):
+            k = sum(((x >> i) & 1) << qb for i, qb in enumerate(qs)) | (1 << 4)
+            s.reset(k)
+            s.apply(gates)
+            a = s.amplitudes()
+            want = np.exp(2j * np.pi * x * y / (1 << n)) / np.sqrt(1 << n)
+            assert np.max(np.abs(a[idx | (1 << 4)] - want)) < tol, x
+            rest = np.ones(1 << M, bool)
+            rest[idx | (1 << 4)] = False
+            assert np.all(a[rest] == 0.0)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dtype,tol", [(q.QSIM_C128, 1e-13), (q.QSIM_C64, 1e-6)])
+def test_fig4_period_after_qft(mode, dtype, tol):
+    """7^A mod 15 (period four, Fig. 4) followed by the quantum FFT on the 5
+    bits of A: A's probability sits on 0, 8, 16, 24, a quarter on each; with
+    errors the state matches the oracle."""
+    a_qubits = 5
+    M = a_qubits + 4
+    gates = np.concatenate([cg.modexp15_circuit(a_qubits), cg.qft_circuit(range(a_qubits))])
+    want = np.zeros(1 << a_qubits)
+    want[::8] = 0.25
+    with state(M, dtype, exec_mode=mode) as s:
+        s.apply(gates)
+        pA = s.probs((1 << a_qubits) - 1)
+        assert np.max(np.abs(pA - want)) < tol
+    em = oracle.Errors(sigma=0.01, p_bitflip=1e-3, p_phaseflip=1e-3, seed=4150, trial=2)
+    _check_vs_oracle(M, gates, dtype, mode, em,
+                     tol_amp=1e-12 if dtype == q.QSIM_C128 else 2e-5,
+                     tol_f=1e-12 if dtype == q.QSIM_C128 else 1e-6)
+
+
+def test_cphase_echo_and_trials_reject_it():
+    M = 12
+    gates = cg.random_circuit(M, 150, 77, kinds=(cg.H, cg.RZ, cg.CNOT, cg.CPHASE))
+    with state(M) as s:
+        s.apply(gates)
+        s.apply_inverse(gates)
+        a = s.amplitudes()
+        assert abs(a[0] - 1.0) < 1e-12 and np.max(np.abs(a[1:])) < 1e-12
+    with pytest.raises(q.QsimError) as e:
+        q.qsim_run_trials(gates, M, q.QSIM_C64, 1e-3, 0.0, 0.0, 1, 0, 4)
+    assert e.value.code == q.QSIM_EINVAL

@@ -247,7 +247,8 @@ def test_norm_conserved():
 
 def _inverse(gates):
     inv = gates[::-1].copy()
-    inv["theta"] = np.where(inv["kind"] == cg.RZ, -inv["theta"], inv["theta"])
+    angled = (inv["kind"] == cg.RZ) | (inv["kind"] == cg.CPHASE)
+    inv["theta"] = np.where(angled, -inv["theta"], inv["theta"])
     return inv
 
 
@@ -435,3 +436,107 @@ def test_fig4_modexp_7_mod_15_has_period_four(a_qubits):
     assert np.max(np.abs(p - want)) < 1e-15
     f = [pow(7, A, 15) for A in range(1 << a_qubits)]
     assert f[:4] == [1, 7, 4, 13] and all(f[A] == f[A % 4] for A in range(len(f)))
+
+
+# ------------------------------------------- controlled phase and quantum FFT
+
+def test_cphase_matrix_is_phase_exponential():
+    import scipy.linalg
+    P1 = np.diag([0.0, 1.0]).astype(complex)
+    for theta, eps in [(0.0, 0.0), (np.pi, 0.0), (np.pi / 8, 1e-3), (2.5, -0.3)]:
+        form, U = oracle.gate_matrix(cg.CPHASE, theta, eps)
+        assert form == 0
+        assert np.max(np.abs(U - scipy.linalg.expm(1j * (theta + eps) * P1))) < 2e-15
+        assert U[0, 0] == 1.0 and U[0, 1] == 0.0 and U[1, 0] == 0.0
+
+
+@pytest.mark.parametrize("M", [2, 3, 5])
+def test_cphase_on_every_basis_state(M):
+    """CPHASE(theta) on (control c, target t) multiplies |k> by e^{i theta}
+    exactly when bits c and t of k are both 1, and leaves every other basis
+    state untouched; it is symmetric in c and t."""
+    theta = 0.8125
+    for c in range(M):
+        for t in range(M):
+            if c == t:
+                continue
+            g = cg.gates_from_list([(cg.CPHASE, t, c, -1, theta)])
+            g_sw = cg.gates_from_list([(cg.CPHASE, c, t, -1, theta)])
+            for k in range(1 << M):
+                out = oracle.as_complex(oracle.simulate(M, g, k=k))
+                out_sw = oracle.as_complex(oracle.simulate(M, g_sw, k=k))
+                want = np.zeros(1 << M, complex)
+                both = (k >> c) & 1 and (k >> t) & 1
+                want[k] = complex(np.cos(theta), np.sin(theta)) if both else 1.0
+                assert np.array_equal(out, want), (c, t, k)
+                assert np.array_equal(out_sw, want), (c, t, k)
+
+
+@pytest.mark.parametrize("M,seed", [(2, 21), (4, 22), (7, 23), (9, 24)])
+def test_pair_loops_match_dense_matrices_with_cphase(M, seed):
+    kinds = (cg.H, cg.RZ, cg.CNOT, cg.CPHASE) + ((cg.TOFFOLI,) if M >= 3 else ())
+    gates = cg.random_circuit(M, 50, seed, kinds=kinds)
+    assert np.any(gates["kind"] == cg.CPHASE)
+    for em in [None, oracle.Errors(sigma=0.2, p_bitflip=0.03, p_phaseflip=0.03, seed=seed,
+                                   trial=4)]:
+        got = oracle.as_complex(oracle.simulate(M, gates, em))
+        want = dense.simulate(M, gates, em)
+        assert np.max(np.abs(got - want)) < 1e-12, (M, em)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6])
+def test_qft_of_basis_states_closed_form(n):
+    """Sec. 2.2's quantum FFT: |x> -> 2^(-n/2) sum_y e^(2 pi i x y / 2^n) |y>,
+    which is sqrt(2^n) times numpy's inverse FFT of the unit vector e_x."""
+    N = 1 << n
+    gates = cg.qft_circuit(range(n))
+    y = np.arange(N)
+    for x in range(N):
+        got = oracle.as_complex(oracle.simulate(n, gates, k=x))
+        closed = np.exp(2j * np.pi * x * y / N) / np.sqrt(N)
+        e = np.zeros(N)
+        e[x] = 1.0
+        assert np.max(np.abs(got - closed)) < 1e-14, x
+        assert np.max(np.abs(got - np.sqrt(N) * np.fft.ifft(e))) < 1e-14, x
+
+
+def test_qft_on_scattered_qubits_of_a_larger_register():
+    """The QFT acts on the value spelled by the listed qubits only: on
+    qubits (5, 1, 3) of M = 7, with the other qubits holding a basis value."""
+    M, qs = 7, [5, 1, 3]
+    gates = cg.qft_circuit(qs)
+    for x in range(8):
+        rest = 0b1000100  # qubits 2 and 6 set
+        k = rest | sum(((x >> i) & 1) << q for i, q in enumerate(qs))
+        got = oracle.as_complex(oracle.simulate(M, gates, k=k))
+        want = np.zeros(1 << M, complex)
+        for yv in range(8):
+            idx = rest | sum(((yv >> i) & 1) << q for i, q in enumerate(qs))
+            want[idx] = np.exp(2j * np.pi * x * yv / 8) / np.sqrt(8)
+        assert np.max(np.abs(got - want)) < 1e-14, x
+
+
+@pytest.mark.parametrize("a_qubits", [4, 5])
+def test_fig4_period_four_after_qft(a_qubits):
+    """Fig. 4 / Sec. 2.2: f(A) = 7^A mod 15 repeats every four values of A,
+    so after the quantum FFT on A (2^a values, a multiple of four) all of
+    A's probability sits on the multiples of 2^a / 4, a quarter on each."""
+    M = a_qubits + 4
+    gates = np.concatenate([cg.modexp15_circuit(a_qubits), cg.qft_circuit(range(a_qubits))])
+    psi = oracle.simulate(M, gates)
+    pA = oracle.probs(psi, M, (1 << a_qubits) - 1)
+    want = np.zeros(1 << a_qubits)
+    want[:: (1 << a_qubits) // 4] = 0.25
+    assert np.max(np.abs(pA - want)) < 1e-14
+    assert abs(np.sum(psi * psi) - 1.0) < 1e-13
+
+
+def test_cphase_inverse_and_invalid_forms():
+    M = 8
+    gates = cg.random_circuit(M, 200, 31, kinds=(cg.H, cg.RZ, cg.CNOT, cg.CPHASE))
+    psi = oracle.simulate(M, gates)
+    oracle.run(psi, M, _inverse(gates))
+    assert np.max(np.abs(psi - oracle.init(M, 0))) < 1e-12
+    for items in ([(cg.CPHASE, 0)], [(cg.CPHASE, 1, 1)], [(cg.CPHASE, 0, 1, 2)]):
+        with pytest.raises(ValueError):
+            oracle.simulate(3, cg.gates_from_list(items))

@@ -29,7 +29,7 @@ def _stream(gates, M, em):
     for s, g in enumerate(gates):
         kind, t = int(g["kind"]), int(g["target"])
         ctrls = {int(c) for c in (g["ctrl0"], g["ctrl1"]) if c >= 0}
-        diag = kind in (cg.RZ, cg.Z)
+        diag = kind in (cg.RZ, cg.Z, cg.CPHASE)
         ops.append([set() if diag else {t}, ctrls | ({t} if diag else set()),
                     t if (not diag or ctrls) else None, s, True])
         for qb in range(M):
@@ -86,7 +86,8 @@ def _check(M, gates, em, opt, period=0):
 
 @pytest.mark.parametrize("M,seed", [(12, 1), (16, 2), (20, 3), (30, 4)])
 def test_order_keeps_every_non_commuting_pair(M, seed):
-    gates = cg.random_circuit(M, 200, seed, kinds=(cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT, cg.TOFFOLI))
+    gates = cg.random_circuit(M, 200, seed, kinds=(cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT, cg.TOFFOLI,
+                                                     cg.CPHASE))
     em = oracle.Errors(sigma=0.01, p_bitflip=0.01, p_phaseflip=0.01, seed=seed, trial=5)
     _check(M, gates, em, None)
 
