@@ -118,6 +118,14 @@ typedef struct {
                             0: default (4) */
     int group_bits;      /* qubits per register quantum, 3..5, with
                             6 <= tile_bits - group_bits <= 9; 0: default (4) */
+    int lazy_qubits;     /* 0 (default) or 1: a qubit no operation has yet
+                            spread over both values ("untouched": after
+                            create or reset it holds one definite value) costs
+                            nothing, since the amplitudes with its other value
+                            are zero; fused passes skip them (the flat form of
+                            the dynamically allocated state vector, Sec. 3.2).
+                            -1: every pass streams the whole register.  The
+                            per-operation path (exec_mode 1) never skips. */
 } qsim_options;
 
 /* Per-state counters of the work launched since the last reset of the
@@ -276,29 +284,35 @@ typedef struct {
     uint32_t n_ops;
     uint32_t n_groups;   /* register groups inside a tile pass */
     uint32_t norm_after; /* 1: a renormalisation follows this pass */
-    uint32_t pad;
+    uint32_t span_qubits;/* qubits the pass's launch spans: it reads and writes
+                            2^span_qubits amplitudes (M unless untouched
+                            qubits are skipped, see lazy_qubits) */
     uint64_t tile_mask;  /* qubits spanned by the tile of a fused pass */
     double flops;        /* algorithmic real flops: per operation, those of its
                             2x2 on each amplitude it updates (6 for a real 2x2,
                             a perturbed X or a diagonal phase; 10 for a real
                             2x2 plus i*w on the diagonal; 0 for a swap or a
-                            sign flip) on the 2^-c of the register that
-                            satisfies its c controls */
+                            sign flip) on the 2^-c of the 2^span_qubits
+                            amplitudes that satisfy its c controls */
+    uint64_t tiles;      /* tiles (workgroup tasks) of a fused pass, else 0 */
 } qsim_pass_info;
 
 /* Host-only dry run of qsim_apply_circuit for a register created with
- * (num_qubits, dtype, opt): lower the gates (drawing the errors of em, NULL =
- * none, starting at step0) into the operation stream (each gate, then its
- * step's flips), fix the execution order and partition it into passes the
- * way the library would (Sec. 2.1: a gate only mixes the amplitude pairs of
- * its target, so gates whose targets lie in one set of qubits can be applied
- * tile by tile in one pass over the state; commuting operations may be
- * reordered for that), and check every pass's kernel arguments for
- * consistency.  Writes min(out_cap, passes) entries of out, and
- * min(order_cap, operations) entries of op_order (op_order[i] = stream index
- * of the i-th operation executed); either may be NULL.  Also the pass and
- * operation counts.  No device is used.  EINVAL for bad arguments; EDEVICE if
- * a pass fails its own consistency check (a library bug). */
+ * (num_qubits, dtype, opt), i.e. starting from |0...0> with every qubit
+ * untouched: lower the gates (drawing the errors of em, NULL = none, starting
+ * at step0) into the operation stream (each gate, then its step's flips),
+ * rewrite it against the untouched qubits (lazy registers), fix the
+ * execution order and partition it into passes the way the library would
+ * (Sec. 2.1: a gate only mixes the amplitude pairs of its target, so gates
+ * whose targets lie in one set of qubits can be applied tile by tile in one
+ * pass over the state; commuting operations may be reordered for that), and
+ * check every pass's kernel arguments for consistency.  Writes min(out_cap,
+ * passes) entries of out, and min(order_cap, operations) entries of op_order
+ * (op_order[i] = index, in the rewritten stream, of the i-th operation
+ * executed; without lazy qubits the rewritten stream is the lowered one);
+ * either may be NULL.  Also the pass and operation counts.  No device is
+ * used.  EINVAL for bad arguments; EDEVICE if a pass fails its own
+ * consistency check (a library bug). */
 int qsim_plan(int num_qubits, int dtype, const qsim_options *opt, const qsim_gate *gates,
               size_t n_gates, const qsim_error_model *em, uint64_t step0, qsim_pass_info *out,
               size_t out_cap, size_t *n_passes, size_t *n_ops, uint32_t *op_order,
@@ -358,6 +372,14 @@ int qsim_synchronize(qsim_state *s);
 /* Register size, dtype, step counter, device pointer and byte size. */
 int qsim_info(const qsim_state *s, int *num_qubits, int *dtype, uint64_t *step,
               void **device_ptr, size_t *bytes);
+
+/* Qubits touched so far (spread over both values by some operation since
+ * create or reset, Sec. 3.2's allocated part of the state): a mask over the
+ * M qubits, every bit set when lazy_qubits is off.  The other qubits hold one
+ * definite value each; fused passes read and write only the 2^popcount
+ * amplitudes of the touched subspace (or a little more, see qsim_pass_info
+ * span_qubits). */
+int qsim_touched_qubits(const qsim_state *s, uint64_t *mask);
 
 /* Turn per-launch HIP event timing on (1) or off (0); either way the
  * counters are zeroed. */

@@ -33,7 +33,7 @@ EXPORTED = [
     "qsim_inject_errors", "qsim_fidelity", "qsim_overlap", "qsim_norm", "qsim_probs",
     "qsim_get_amplitudes", "qsim_set_amplitudes", "qsim_run_trials", "qsim_synchronize",
     "qsim_info", "qsim_profile", "qsim_get_stats", "qsim_last_error", "qsim_plan", "qsim_serve",
-    "qsim_trial_plan", "qsim_overlap_noalloc",
+    "qsim_trial_plan", "qsim_overlap_noalloc", "qsim_touched_qubits",
 ]
 
 
@@ -54,7 +54,7 @@ class qsim_options(ctypes.Structure):
                 ("ext_buffer", ctypes.c_void_p), ("ext_bytes", ctypes.c_size_t),
                 ("renorm_period", ctypes.c_int), ("exec_mode", ctypes.c_int),
                 ("tile_bits", ctypes.c_int), ("low_bits", ctypes.c_int),
-                ("group_bits", ctypes.c_int)]
+                ("group_bits", ctypes.c_int), ("lazy_qubits", ctypes.c_int)]
 
 
 class qsim_stats(ctypes.Structure):
@@ -72,11 +72,12 @@ class qsim_stats(ctypes.Structure):
 class qsim_pass_info(ctypes.Structure):
     _fields_ = [("fused", ctypes.c_uint32), ("first_op", ctypes.c_uint32),
                 ("n_ops", ctypes.c_uint32), ("n_groups", ctypes.c_uint32),
-                ("norm_after", ctypes.c_uint32), ("pad", ctypes.c_uint32),
-                ("tile_mask", ctypes.c_uint64), ("flops", ctypes.c_double)]
+                ("norm_after", ctypes.c_uint32), ("span_qubits", ctypes.c_uint32),
+                ("tile_mask", ctypes.c_uint64), ("flops", ctypes.c_double),
+                ("tiles", ctypes.c_uint64)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class qsim_request(ctypes.Structure):
@@ -137,6 +138,7 @@ def lib() -> ctypes.CDLL:
                             sz, ctypes.POINTER(sz)],
         "qsim_overlap_noalloc": [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  vp, dp],
+        "qsim_touched_qubits": [vp, ctypes.POINTER(u64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -284,6 +286,12 @@ def qsim_info(h) -> dict:
             "device_ptr": ptr.value, "bytes": nb.value}
 
 
+def qsim_touched_qubits(h) -> int:
+    m = ctypes.c_uint64()
+    _check(lib().qsim_touched_qubits(h, ctypes.byref(m)))
+    return m.value
+
+
 def qsim_profile(h, enable: bool) -> None:
     _check(lib().qsim_profile(h, 1 if enable else 0))
 
@@ -363,9 +371,10 @@ def qsim_last_error() -> str:
 # --------------------------------------------------------------- helpers
 
 def make_options(device=0, hip_stream=None, ext_buffer=None, ext_bytes=0, renorm_period=0,
-                 exec_mode=0, tile_bits=0, low_bits=0, group_bits=0) -> qsim_options:
+                 exec_mode=0, tile_bits=0, low_bits=0, group_bits=0,
+                 lazy_qubits=0) -> qsim_options:
     return qsim_options(device, hip_stream, ext_buffer, ext_bytes, renorm_period, exec_mode,
-                        tile_bits, low_bits, group_bits)
+                        tile_bits, low_bits, group_bits, lazy_qubits)
 
 
 def torch_options(tensor=None, stream=None, **kw) -> qsim_options:
@@ -447,6 +456,9 @@ class State:
 
     def info(self) -> dict:
         return qsim_info(self.h)
+
+    def touched_qubits(self) -> int:
+        return qsim_touched_qubits(self.h)
 
     def profile(self, enable: bool = True):
         qsim_profile(self.h, enable)

@@ -88,6 +88,9 @@ struct qsim_state {
     qsim_error_model em{};
     int renorm_period = 0;   // 0 = never
     int exec_mode = 0;
+    bool lazy = false;       // fused passes visit the touched qubits only
+    uint64_t active = 0;     // touched qubits: amplitudes spread over both values
+    uint64_t fixed = 0;      // the value of every untouched qubit
     int tile_bits = 13;
     int low_bits = 5;
     int group_bits = 5;
@@ -416,6 +419,161 @@ bool renorm_due(const qsim_state *s, const Op &op)
     return s->renorm_period > 0 && op.step_end && ((op.step + 1) % (uint64_t)s->renorm_period) == 0;
 }
 
+// Mark the operations after which a renormalisation boundary falls, before
+// the stream is rewritten or reordered.
+void mark_norms(const qsim_state *s, std::vector<Op> &ops)
+{
+    for (Op &op : ops) {
+        op.norm_mark = renorm_due(s, op);
+        op.zdep = 0;
+        op.activates = false;
+        op.relocate = false;
+    }
+}
+
+uint64_t full_mask(int M) { return M >= 64 ? ~0ull : ((1ull << M) - 1); }
+
+Op exact_swap(int q, uint64_t step)
+{
+    Op x{};
+    x.type = kOpSwap;
+    x.target = q;
+    x.u[2] = 1;
+    x.u[4] = 1;
+    x.step = step;
+    return x;
+}
+
+// ------------------------------------------------------------ lazy qubits
+//
+// The flat form of the dynamically allocated state vector of Sec. 3.2: until
+// an operation spreads a qubit over both of its values, the qubit has one
+// definite value, every amplitude with the other value is exactly zero, and
+// those need not be read, written or transformed.  The state records the
+// qubits already spread ("touched", s->active) and the value of every other
+// one (s->fixed); a fused pass walks only the tiles whose untouched qubits
+// hold their values.  Before scheduling, the operation stream of a call is
+// rewritten against that knowledge, in stream order:
+//   - a control on an untouched qubit is decided: value 0 drops the
+//     operation, value 1 drops the control (the operation keeps the qubit as
+//     an ordering dependency, so the scheduler never moves it across the
+//     qubit's first spreading operation);
+//   - a diagonal (Rz, Z, CPHASE, a phase flip) whose target is untouched is a
+//     scalar: without controls it joins a global phase, applied once at the
+//     end of the call; with controls it becomes that phase on one of them;
+//   - an exact uncontrolled X (a bit flip, an unperturbed X) on an untouched
+//     qubit flips its logical value without moving data;
+//   - every other operation on an untouched qubit spreads it (an exact swap
+//     first moves its amplitudes to its logical value if that was flipped);
+//   - at the end of the call, every untouched qubit whose value was flipped
+//     gets one exact swap (its amplitudes move to the new value, and the qubit
+//     stays untouched), and the global phase is applied as one scalar
+//     operation: between calls the register holds the plain state vector.
+// Every step is exact except the phase products, which round as the gates'
+// own products would.
+void lazy_rewrite(const qsim_state *s, std::vector<Op> &stream)
+{
+    std::vector<Op> out;
+    out.reserve(stream.size() + 8);
+    uint64_t act = s->active;
+    uint64_t flipped = 0;              // untouched qubits whose value was flipped
+    double ph_re = 1.0, ph_im = 0.0;   // global phase gathered so far
+    const uint64_t last_step = stream.empty() ? 0 : stream.back().step;
+    auto value = [&](int q) { return (((s->fixed ^ flipped) >> q) & 1ull) != 0; };
+    // a dropped operation hands its renormalisation boundary to the one before
+    auto dropped = [&](const Op &op) {
+        if (op.norm_mark && !out.empty())
+            out.back().norm_mark = true;
+    };
+    for (Op op : stream) {
+        const uint64_t quiet = op.cmask & ~act;  // controls on untouched qubits
+        bool met = true;
+        for (uint64_t m = quiet; m != 0; m &= m - 1)
+            met = met && value(__builtin_ctzll(m));
+        if (!met) {
+            dropped(op);
+            continue;
+        }
+        op.cmask &= act;
+        op.zdep = quiet;
+        const uint64_t tb = 1ull << op.target;
+        if (act & tb) {
+            out.push_back(op);
+            continue;
+        }
+        const bool v = value(op.target);
+        if (op.type == kOpDiag || op.type == kOpNeg) {
+            double fr = 1.0, fi = 0.0;  // the factor the target's value picks
+            if (op.type == kOpNeg) {
+                fr = v ? -1.0 : 1.0;
+            } else {
+                fr = v ? op.u[6] : op.u[0];
+                fi = v ? op.u[7] : op.u[1];
+            }
+            if (fr == 1.0 && fi == 0.0) {
+                dropped(op);
+                continue;
+            }
+            if (op.cmask == 0) {
+                const double r = ph_re * fr - ph_im * fi;
+                ph_im = ph_re * fi + ph_im * fr;
+                ph_re = r;
+                dropped(op);
+                continue;
+            }
+            // the factor where the touched controls are met: a diagonal on one
+            // of them, controlled by the others
+            Op d = op;
+            const int c = __builtin_ctzll(op.cmask);
+            d.target = c;
+            d.cmask = op.cmask & ~(1ull << c);
+            d.zdep |= tb;
+            std::memset(d.u, 0, sizeof(d.u));
+            d.u[0] = 1.0;
+            if (fr == -1.0 && fi == 0.0) {
+                d.type = kOpNeg;
+                d.u[6] = -1.0;
+            } else {
+                d.type = kOpDiag;
+                d.u[6] = fr;
+                d.u[7] = fi;
+            }
+            out.push_back(d);
+            continue;
+        }
+        if (op.type == kOpSwap && op.cmask == 0) {
+            flipped ^= tb;
+            dropped(op);
+            continue;
+        }
+        // spreads its target
+        if (flipped & tb) {
+            Op x = exact_swap(op.target, op.step);
+            x.activates = true;
+            out.push_back(x);
+            flipped &= ~tb;
+        }
+        op.activates = true;
+        act |= tb;
+        out.push_back(op);
+    }
+    for (uint64_t m = flipped; m != 0; m &= m - 1) {
+        Op x = exact_swap(__builtin_ctzll(m), last_step);
+        x.relocate = true;
+        out.push_back(x);
+    }
+    if (ph_re != 1.0 || ph_im != 0.0) {
+        Op p{};
+        p.type = kOpDiag;
+        p.target = 0;
+        p.u[0] = ph_re; p.u[1] = ph_im;
+        p.u[6] = ph_re; p.u[7] = ph_im;
+        p.step = last_step;
+        out.push_back(p);
+    }
+    stream.swap(out);
+}
+
 // Shape of the fused passes of a state: k tile qubits, G group bits per
 // register quantum, 2^(k-G) threads per workgroup with 6 <= k - G <= 9.
 // False when the register is too small for a fused pass (M < 9).
@@ -439,7 +597,7 @@ OpUse op_use(const Op &op)
 {
     const uint64_t t = 1ull << op.target;
     const bool diag = op.type == kOpDiag || op.type == kOpNeg;
-    return {diag ? 0ull : t, op.cmask | (diag ? t : 0ull)};
+    return {diag ? 0ull : t, op.cmask | op.zdep | (diag ? t : 0ull)};
 }
 
 // Partition ops[lo, hi) into fused passes, appending the operations to
@@ -590,32 +748,84 @@ void schedule(const qsim_state *s, const std::vector<Op> &ops, std::vector<uint3
         while (prefix < n && ran[prefix])
             ++prefix;
         for (; next < prefix; ++next)
-            if (renorm_due(s, ops[next]))
+            if (ops[next].norm_mark)
                 p.norm_after = true;
     }
 }
 
-// Build the kernel arguments of one fused pass.
+// Runs of consecutive qubits in `mask` (below qubit M).
+int count_runs(uint64_t mask, int M)
+{
+    int n = 0;
+    for (int q = 0; q < M; ++q)
+        if (((mask >> q) & 1u) && (q == 0 || !((mask >> (q - 1)) & 1u)))
+            ++n;
+    return n;
+}
+
+// Qubits the tiles of a pass over tile set S enumerate: the touched qubits
+// outside S.  Where they fall into more runs than the kernel's run table
+// holds, the untouched qubits of the narrowest gaps between runs are
+// enumerated too (their other value's tiles are zero and stay zero); gaps that
+// hold a tile qubit cannot close, but there are at most |S| + 1 of them.
+uint64_t pass_enumerated(uint64_t act, uint64_t S, int M)
+{
+    uint64_t E = act & full_mask(M) & ~S;
+    while (count_runs(E, M) > kMaxRuns) {
+        int best_lo = -1, best_len = 0;
+        for (int q = 0; q < M;) {
+            if ((E >> q) & 1u) {
+                ++q;
+                continue;
+            }
+            int e = q;
+            while (e < M && !((E >> e) & 1u))
+                ++e;
+            const bool inner = q > 0 && e < M;
+            const uint64_t gap = full_mask(e - q) << q;
+            if (inner && (gap & S) == 0 && (best_lo < 0 || e - q < best_len)) {
+                best_lo = q;
+                best_len = e - q;
+            }
+            q = e;
+        }
+        if (best_lo < 0)
+            break;
+        E |= full_mask(best_len) << best_lo;
+    }
+    return E;
+}
+
+// Build the kernel arguments of one fused pass.  act: qubits touched when the
+// pass runs; fixed: the values of the others.
 template <typename R>
 void build_tile_args(const qsim_state *s, const std::vector<Op> &ops, const PassPlan &p,
-                     TileArgs<R> &A, int &G)
+                     uint64_t act, uint64_t fixed, TileArgs<R> &A, int &G)
 {
     const int M = s->M;
     int k;
     tile_shape(s, k, G);
     const int low = std::min(s->low_bits, k);
-    // tile qubit set: low qubits, then the pass's targets, then the lowest free qubits
+    // tile qubit set: low qubits, then the pass's targets, then the lowest free
+    // qubits (touched ones first)
     uint64_t S = (1ull << low) - 1;
     for (size_t o = p.first; o < p.first + p.count; ++o)
         if (needs_tile_target(ops[o]))
             S |= 1ull << ops[o].target;
     for (int q = 0; q < M && __builtin_popcountll(S) < k; ++q)
+        if ((act >> q) & 1u)
+            S |= 1ull << q;
+    for (int q = 0; q < M && __builtin_popcountll(S) < k; ++q)
         S |= 1ull << q;
+    const uint64_t E = pass_enumerated(act, S, M);
     std::memset(&A, 0, sizeof(A));
     A.M = (uint32_t)M;
     A.k = (uint32_t)k;
     A.low = (uint32_t)low;
     A.smask = S;
+    A.emask = E;
+    A.base_or = fixed & full_mask(M) & ~S & ~E;
+    A.mact = (uint32_t)__builtin_popcountll(S | E);
     int tpos_of[64];
     int m = 0;
     for (int q = 0; q < M; ++q) {
@@ -626,15 +836,19 @@ void build_tile_args(const qsim_state *s, const std::vector<Op> &ops, const Pass
             tpos_of[q] = -1;
         }
     }
-    // runs of consecutive qubits of S and of its complement, ascending
+    // runs of consecutive qubits of S and of E, ascending (untouched qubits
+    // outside both are skipped: base_or holds their values)
     for (int q = 0; q < M;) {
-        const bool in = (S >> q) & 1u;
-        int e = q;
-        while (e < M && (((S >> e) & 1u) != 0) == in)
+        const int kind = ((S >> q) & 1u) ? 1 : ((E >> q) & 1u) ? 2 : 0;
+        int e = q + 1;
+        while (e < M && (((S >> e) & 1u) ? 1 : ((E >> e) & 1u) ? 2 : 0) == kind)
             ++e;
-        uint32_t &n = in ? A.nsrun : A.ncrun;
-        (in ? A.srun : A.crun)[n] = (uint32_t)q | ((uint32_t)(e - q) << 8);
-        ++n;
+        if (kind != 0) {
+            uint32_t &n = kind == 1 ? A.nsrun : A.ncrun;
+            if (n < (uint32_t)kMaxRuns)
+                (kind == 1 ? A.srun : A.crun)[n] = (uint32_t)q | ((uint32_t)(e - q) << 8);
+            ++n;  // past kMaxRuns the consistency check rejects the pass
+        }
         q = e;
     }
     // operations, grouped so that the targets that need a group bit span at
@@ -814,9 +1028,11 @@ bool tile_args_consistent(const TileArgs<R> &A, int G, const std::vector<Op> &op
         if (i > 0 && (A.crun[i] & 0xFFu) <= (A.crun[i - 1] & 0xFFu))
             cm = 0;
     }
-    const uint64_t full = (A.M >= 64) ? ~0ull : ((1ull << A.M) - 1);
+    const uint64_t full = full_mask((int)A.M);
     if (A.nsrun > (uint32_t)kMaxRuns || A.ncrun > (uint32_t)kMaxRuns || sm != A.smask ||
-        cm != (full & ~A.smask) || sl != A.k || cl != A.M - A.k) {
+        cm != A.emask || (A.emask & A.smask) != 0 || (A.emask & ~full) != 0 || sl != A.k ||
+        A.mact != A.k + (uint32_t)__builtin_popcountll(A.emask) || cl != A.mact - A.k ||
+        (A.base_or & (A.smask | A.emask | ~full)) != 0) {
         snprintf(why, n, "run tables");
         return false;
     }
@@ -854,6 +1070,13 @@ bool tile_args_consistent(const TileArgs<R> &A, int G, const std::vector<Op> &op
                 snprintf(why, n, "op %u: controlled diagonal folded", o);
                 return false;
             }
+            // controls and diagonal targets outside the tile must be qubits
+            // the tile number enumerates (untouched ones were decided)
+            if ((t.cm_out & ~A.emask) != 0 ||
+                (t.kind >= kTDiagOut && t.tpos == kNoPos && !((A.emask >> op.target) & 1u))) {
+                snprintf(why, n, "op %u reads an untouched qubit outside the tile", o);
+                return false;
+            }
             // the three control masks must rebuild the op's control set
             uint64_t back = t.cm_out;
             for (int i = 0; i < G; ++i)
@@ -875,9 +1098,31 @@ bool tile_args_consistent(const TileArgs<R> &A, int G, const std::vector<Op> &op
     return true;
 }
 
-template <typename R>
-int run_ops(qsim_state *s, const std::vector<Op> &stream)
+// A call's operation stream made ready for scheduling: renormalisation
+// boundaries marked, then (lazy states) rewritten against the untouched
+// qubits.
+void prepare_stream(const qsim_state *s, std::vector<Op> &stream)
 {
+    mark_norms(s, stream);
+    if (s->lazy)
+        lazy_rewrite(s, stream);
+}
+
+// Touched qubits and untouched values after a pass has run.
+void track_pass(const std::vector<Op> &ops, const PassPlan &p, uint64_t &act, uint64_t &fixed)
+{
+    for (size_t i = p.first; i < p.first + p.count; ++i) {
+        if (ops[i].activates)
+            act |= 1ull << ops[i].target;
+        if (ops[i].relocate)
+            fixed ^= 1ull << ops[i].target;
+    }
+}
+
+template <typename R>
+int run_ops(qsim_state *s, std::vector<Op> &stream)
+{
+    prepare_stream(s, stream);
     std::vector<PassPlan> plan;
     std::vector<uint32_t> order;
     schedule(s, stream, order, plan);
@@ -888,25 +1133,30 @@ int run_ops(qsim_state *s, const std::vector<Op> &stream)
     const double full = 2.0 * (double)(1ull << s->M) * (double)elem_bytes(s->dtype);
     bool scale_pending = false;
     double *norm_sum = s->d_scalars + 4;   // [4] = sum, [5] = 1/sqrt(sum)
+    uint64_t act = s->active, fixed = s->fixed;
     for (const PassPlan &p : plan) {
         if (p.fused) {
             TileArgs<R> A;
             int G = 0;
-            build_tile_args<R>(s, ops, p, A, G);
+            build_tile_args<R>(s, ops, p, act, fixed, A, G);
+            if (A.nsrun > (uint32_t)kMaxRuns || A.ncrun > (uint32_t)kMaxRuns ||
+                A.mact < A.k || A.mact > (uint32_t)s->M)
+                return fail(QSIM_EDEVICE, "internal: fused pass tables out of range");
             A.psi = psi;
             A.scale_in = scale_pending ? norm_sum + 1 : nullptr;
             A.norm_out = p.norm_after ? s->d_tile_norm : nullptr;
             double flops = 0.0;
             for (size_t i = p.first; i < p.first + p.count; ++i)
-                flops += op_flops(ops[i], s->M);
-            Timed t(s, 1, full, flops);
+                flops += op_flops(ops[i], (int)A.mact);
+            const double bytes = 2.0 * std::ldexp((double)elem_bytes(s->dtype), (int)A.mact);
+            Timed t(s, 1, bytes, flops);
             HIP_TRY(launch_tile<R>(A, G, s->stream), "fused pass launch");
             t.done();
             scale_pending = false;
             s->stats.fused_passes++;
             if (p.norm_after) {
                 Timed t2(s, 2, 0);
-                HIP_TRY(launch_finish_norm(s->d_tile_norm, 1ull << (s->M - A.k), norm_sum,
+                HIP_TRY(launch_finish_norm(s->d_tile_norm, 1ull << (A.mact - A.k), norm_sum,
                                            s->stream), "norm launch");
                 t2.done();
                 scale_pending = true;
@@ -932,6 +1182,7 @@ int run_ops(qsim_state *s, const std::vector<Op> &stream)
                 s->stats.renorms++;
             }
         }
+        track_pass(ops, p, act, fixed);
         s->stats.passes++;
     }
     if (scale_pending) {
@@ -939,6 +1190,8 @@ int run_ops(qsim_state *s, const std::vector<Op> &stream)
         HIP_TRY(launch_scale<R>(psi, s->M, norm_sum + 1, s->stream), "scale launch");
         t0.done();
     }
+    s->active = act;
+    s->fixed = fixed & ~act;
     return QSIM_OK;
 }
 
@@ -978,6 +1231,8 @@ int configure(qsim_state *s, int num_qubits, int dtype, const qsim_options &o)
         return fail(QSIM_EINVAL, "exec_mode %d", o.exec_mode);
     if (o.renorm_period < -1)
         return fail(QSIM_EINVAL, "renorm_period %d", o.renorm_period);
+    if (o.lazy_qubits < -1 || o.lazy_qubits > 1)
+        return fail(QSIM_EINVAL, "lazy_qubits %d is not -1, 0 or 1", o.lazy_qubits);
     const size_t eb = elem_bytes(dtype);
     const size_t bytes = ((size_t)1 << num_qubits) * eb;
     if (o.ext_buffer && o.ext_bytes < bytes)
@@ -1007,6 +1262,10 @@ int configure(qsim_state *s, int num_qubits, int dtype, const qsim_options &o)
     s->renorm_period = o.renorm_period == 0 ? (dtype == QSIM_C64 ? 64 : 0)
                        : (o.renorm_period < 0 ? 0 : o.renorm_period);
     s->bytes = bytes;
+    // the per-operation path always streams the whole register
+    s->lazy = o.lazy_qubits >= 0 && o.exec_mode != 1;
+    s->active = s->lazy ? 0 : full_mask(num_qubits);
+    s->fixed = 0;  // the register starts (or is rebound) at |0...0>
     return QSIM_OK;
 }
 
@@ -1219,6 +1478,8 @@ int qsim_reset(qsim_state *s, uint64_t basis_index)
                 "init launch");
         t.done();
         s->step = 0;
+        s->active = s->lazy ? 0 : full_mask(s->M);
+        s->fixed = basis_index & ~s->active;
         return QSIM_OK;
     });
 }
@@ -1251,12 +1512,13 @@ int qsim_apply_circuit(qsim_state *s, const qsim_gate *gates, size_t n_gates)
         HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
         std::vector<Op> ops;
         lower_circuit(s, gates, n_gates, ops);
+        const size_t flips = ops.size() - n_gates;
         rc = s->dtype == QSIM_C64 ? run_ops<float>(s, ops) : run_ops<double>(s, ops);
         if (rc != QSIM_OK)
             return rc;
         s->step += n_gates;
         s->stats.gates += n_gates;
-        s->stats.flips += ops.size() - n_gates;
+        s->stats.flips += flips;
         return QSIM_OK;
     });
 }
@@ -1487,6 +1749,8 @@ int qsim_set_amplitudes(qsim_state *s, uint64_t offset, uint64_t count, const do
         int rc = ensure_stage(s, chunk * 16);
         if (rc != QSIM_OK)
             return rc;
+        // arbitrary amplitudes: no qubit is known to hold one value any more
+        s->active = full_mask(s->M);
         for (uint64_t done = 0; done < count; done += chunk) {
             const uint64_t c = std::min(chunk, count - done);
             HIP_TRY(hipMemcpyAsync(s->d_stage, in + 2 * done, c * 16, hipMemcpyHostToDevice,
@@ -1528,9 +1792,11 @@ int qsim_plan(int num_qubits, int dtype, const qsim_options *opt, const qsim_gat
         st.step = step0;
         std::vector<Op> stream;
         lower_circuit(&st, gates, n_gates, stream);
+        prepare_stream(&st, stream);
         std::vector<PassPlan> plan;
         std::vector<uint32_t> order;
         schedule(&st, stream, order, plan);
+        uint64_t act = st.active, fixed = st.fixed;
         std::vector<Op> ops(order.size());
         for (size_t i = 0; i < order.size(); ++i)
             ops[i] = stream[order[i]];
@@ -1547,31 +1813,48 @@ int qsim_plan(int num_qubits, int dtype, const qsim_options *opt, const qsim_gat
             info.first_op = (uint32_t)plan[i].first;
             info.n_ops = (uint32_t)plan[i].count;
             info.norm_after = plan[i].norm_after ? 1u : 0u;
-            for (size_t j = plan[i].first; j < plan[i].first + plan[i].count; ++j)
-                info.flops += op_flops(ops[j], num_qubits);
+            int span = num_qubits;  // qubits the pass's launch spans
             if (plan[i].fused) {
                 char why[160];
                 int G = 0;
                 bool ok;
                 if (dtype == QSIM_C64) {
                     TileArgs<float> A;
-                    build_tile_args<float>(&st, ops, plan[i], A, G);
+                    build_tile_args<float>(&st, ops, plan[i], act, fixed, A, G);
                     ok = tile_args_consistent<float>(A, G, ops, plan[i], why, sizeof(why));
                     info.n_groups = A.ngroups;
                     info.tile_mask = A.smask;
+                    span = (int)A.mact;
+                    info.tiles = 1ull << (A.mact - A.k);
                 } else {
                     TileArgs<double> A;
-                    build_tile_args<double>(&st, ops, plan[i], A, G);
+                    build_tile_args<double>(&st, ops, plan[i], act, fixed, A, G);
                     ok = tile_args_consistent<double>(A, G, ops, plan[i], why, sizeof(why));
                     info.n_groups = A.ngroups;
                     info.tile_mask = A.smask;
+                    span = (int)A.mact;
+                    info.tiles = 1ull << (A.mact - A.k);
                 }
                 if (!ok)
                     return fail(QSIM_EDEVICE, "internal: pass %zu inconsistent: %s", i, why);
             }
+            for (size_t j = plan[i].first; j < plan[i].first + plan[i].count; ++j)
+                info.flops += op_flops(ops[j], span);
+            info.span_qubits = (uint32_t)span;
+            track_pass(ops, plan[i], act, fixed);
             if (out && i < out_cap)
                 out[i] = info;
         }
+        return QSIM_OK;
+    });
+}
+
+int qsim_touched_qubits(const qsim_state *s, uint64_t *mask)
+{
+    return guarded(__func__, [&]() -> int {
+        if (s == nullptr || mask == nullptr)
+            return fail(QSIM_EINVAL, "NULL argument");
+        *mask = s->active;
         return QSIM_OK;
     });
 }

@@ -107,8 +107,13 @@ struct Op {
     uint64_t cmask;   // global control mask (all bits must be 1)
     double u[8];      // kOpMat: u00 u01 u10 u11 as re,im; kOpDiag: d0 = u[0..1], d1 = u[6..7]
     uint64_t step;    // circuit step the operation belongs to
+    uint64_t zdep;    // untouched qubits whose definite value the operation was
+                      // specialised on (kept as ordering dependencies)
     bool is_flip;     // injected by the error model
     bool step_end;    // last operation of its step
+    bool norm_mark;   // a renormalisation boundary follows this operation
+    bool activates;   // spreads its (untouched) target over both values
+    bool relocate;    // moves an untouched qubit's amplitudes to its other value
 };
 
 // ------------------------------------------------------ kernel argument blocks
@@ -169,13 +174,19 @@ __host__ __device__ inline uint32_t group_bit(uint32_t w, int i)
 }
 
 // A fused pass: tiles of 2^k amplitudes spanned by qubits spos[0..k), the
-// first `low` of which are qubits 0..low-1 (contiguous runs in memory).
+// first `low` of which are qubits 0..low-1 (contiguous runs in memory).  The
+// 2^(mact-k) tiles enumerate the qubits of emask; every other qubit of the
+// register is untouched and holds the value base_or gives it (its other
+// value's amplitudes are zero and are not visited).
 template <typename R>
 struct TileArgs {
     cplx<R> *psi;
     const double *scale_in;   // if set, multiply every amplitude by *scale_in on load
     double *norm_out;         // if set, per-tile sum of |a|^2 after the pass
     uint64_t smask;           // global mask of the tile qubits
+    uint64_t emask;           // qubits the tile number enumerates (host-side checks)
+    uint64_t base_or;         // values of the untouched qubits outside the pass
+    uint32_t mact;            // qubits the pass spans: tile qubits + enumerated ones
     uint32_t M;
     uint32_t k;
     uint32_t low;

@@ -461,7 +461,7 @@ k_tile(const TileArgs<R> A)
         crun[i] = A.crun[i];
     }
     const uint32_t nsrun = A.nsrun, ncrun = A.ncrun;
-    const uint64_t ntiles = 1ull << (A.M - A.k);
+    const uint64_t ntiles = 1ull << (A.mact - A.k);
 
     // the first group's layout is the same for every tile
     uint32_t e0[G], j00;
@@ -478,8 +478,9 @@ k_tile(const TileArgs<R> A)
 
     for (; tile_id < ntiles; tile_id += gridDim.x) {
         // global index of tile element 0: the tile number spread over the
-        // qubits outside the tile, in ascending order
-        const uint64_t base = spread(tile_id, crun, ncrun);
+        // enumerated qubits outside the tile, in ascending order, plus the
+        // values of the untouched qubits
+        const uint64_t base = spread(tile_id, crun, ncrun) | A.base_or;
         load_quantum<R, G>(A.psi + (base | rel0), o0, pair00, x);
         if (A.scale_in != nullptr) {
             const R sc = (R)*A.scale_in;
@@ -567,7 +568,7 @@ hipError_t launch_gt(const TileArgs<R> &A, hipStream_t st)
     int occ = kernel_resident_blocks(fn, T, lds);
     if (occ <= 0)
         occ = 256;
-    const uint64_t tiles = 1ull << (A.M - A.k);
+    const uint64_t tiles = 1ull << (A.mact - A.k);
     const uint64_t grid = tiles < (uint64_t)occ ? tiles : (uint64_t)occ;
     hipLaunchKernelGGL((k_tile<R, G, T>), dim3((unsigned)grid), dim3(T), lds, st, A);
     return hipGetLastError();

@@ -26,7 +26,7 @@ SHAPES = [(13, 5, 5), (13, 5, 4), (12, 5, 4), (14, 5, 5), (9, 1, 3), (10, 3, 4),
 def test_plan_covers_every_op_in_order(M, tile, low, group):
     gates = cg.random_circuit(M, 300, M * 7 + tile, kinds=(cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT,
                                                              cg.TOFFOLI))
-    opt = q.make_options(tile_bits=tile, low_bits=low, group_bits=group)
+    opt = q.make_options(lazy_qubits=-1, tile_bits=tile, low_bits=low, group_bits=group)
     passes, nops = q.qsim_plan(M, q.QSIM_C64, gates, opt, sigma=0.01, p_bitflip=0.01,
                                p_phaseflip=0.01, seed=3, trial=1)
     nxt = 0
@@ -44,10 +44,10 @@ def test_flip_count_matches_oracle_draws():
     gates = cg.random_circuit(M, G, 4)
     em = oracle.Errors(sigma=0.0, p_bitflip=0.01, p_phaseflip=0.02, seed=77, trial=5)
     want = sum(bin(oracle.flip_events(em, s, qb)).count("1") for s in range(G) for qb in range(M))
-    _, nops = q.qsim_plan(M, q.QSIM_C128, gates, None, sigma=0.0, p_bitflip=0.01,
+    _, nops = q.qsim_plan(M, q.QSIM_C128, gates, q.make_options(lazy_qubits=-1), sigma=0.0, p_bitflip=0.01,
                           p_phaseflip=0.02, seed=77, trial=5)
     assert nops == G + want
-    _, nops2 = q.qsim_plan(M, q.QSIM_C128, gates[100:], None, sigma=0.0, p_bitflip=0.01,
+    _, nops2 = q.qsim_plan(M, q.QSIM_C128, gates[100:], q.make_options(lazy_qubits=-1), sigma=0.0, p_bitflip=0.01,
                            p_phaseflip=0.02, seed=77, trial=5, step0=100)
     want2 = sum(bin(oracle.flip_events(em, s, qb)).count("1") for s in range(100, G) for qb in range(M))
     assert nops2 == G - 100 + want2
@@ -57,27 +57,27 @@ def test_fusion_factor_of_uniform_random_circuit():
     # targets uniform over 30 qubits: a 13-qubit tile with 4 low qubits holds
     # a dozen or more gates
     gates = cg.random_circuit(30, 1000, 30)
-    passes, _ = q.qsim_plan(30, q.QSIM_C64, gates)
+    passes, _ = q.qsim_plan(30, q.QSIM_C64, gates, q.make_options(lazy_qubits=-1))
     assert all(p["fused"] for p in passes)
     assert 1000 / len(passes) > 8
 
 
 def test_renorm_boundaries_end_passes():
     gates = cg.random_circuit(16, 256, 1)
-    passes, _ = q.qsim_plan(16, q.QSIM_C64, gates, q.make_options(renorm_period=32))
+    passes, _ = q.qsim_plan(16, q.QSIM_C64, gates, q.make_options(lazy_qubits=-1, renorm_period=32))
     assert 1 <= sum(p["norm_after"] for p in passes) <= 256 // 32
-    perop, _ = q.qsim_plan(16, q.QSIM_C64, gates, q.make_options(renorm_period=32, exec_mode=1))
+    perop, _ = q.qsim_plan(16, q.QSIM_C64, gates, q.make_options(lazy_qubits=-1, renorm_period=32, exec_mode=1))
     assert [i for i, p in enumerate(perop) if p["norm_after"]] == list(range(31, 256, 32))
-    plain, _ = q.qsim_plan(16, q.QSIM_C64, gates, q.make_options(exec_mode=1))
+    plain, _ = q.qsim_plan(16, q.QSIM_C64, gates, q.make_options(lazy_qubits=-1, exec_mode=1))
     assert len(plain) == 256 and not any(p["fused"] for p in plain)
 
 
 def test_small_registers_use_per_gate_passes():
     for M in range(1, 9):
         gates = cg.random_circuit(M, 20, M, kinds=(cg.H, cg.RZ, cg.X))
-        passes, _ = q.qsim_plan(M, q.QSIM_C128, gates)
+        passes, _ = q.qsim_plan(M, q.QSIM_C128, gates, q.make_options(lazy_qubits=-1))
         assert not any(p["fused"] for p in passes)
-    passes, _ = q.qsim_plan(9, q.QSIM_C128, cg.random_circuit(9, 20, 9))
+    passes, _ = q.qsim_plan(9, q.QSIM_C128, cg.random_circuit(9, 20, 9), q.make_options(lazy_qubits=-1))
     assert all(p["fused"] for p in passes)
 
 
@@ -88,7 +88,7 @@ def test_plan_rejects_bad_input():
         q.qsim_plan(5, q.QSIM_C64, cg.gates_from_list([(cg.H, 1)]), sigma=-1.0)
     with pytest.raises(q.QsimError):
         q.qsim_plan(20, q.QSIM_C128, cg.gates_from_list([(cg.H, 1)]),
-                    q.make_options(tile_bits=14, group_bits=5))
+                    q.make_options(lazy_qubits=-1, tile_bits=14, group_bits=5))
 
 
 @pytest.mark.parametrize("M,tile,group", [(10, 10, 4), (10, 10, 3), (11, 11, 5), (12, 12, 4),
@@ -97,7 +97,7 @@ def test_control_heavy_passes_keep_group_bits_free(M, tile, group):
     # Toffoli-dense runs: the controls of a group's operations can cover
     # most of the tile (qsim_plan checks every pass's arguments)
     gates = cg.random_circuit(M, 400, 500 + M, kinds=(cg.TOFFOLI, cg.CNOT, cg.H))
-    opt = q.make_options(tile_bits=tile, group_bits=group)
+    opt = q.make_options(lazy_qubits=-1, tile_bits=tile, group_bits=group)
     passes, nops = q.qsim_plan(M, q.QSIM_C64, gates, opt, sigma=0.01, p_bitflip=0.01,
                                p_phaseflip=0.01, seed=9, trial=2)
     assert sum(p["n_ops"] for p in passes) == nops
@@ -110,7 +110,7 @@ def test_toffoli_run_whose_controls_cover_the_tile():
     T = cg.TOFFOLI
     gates = cg.gates_from_list([(T, 0, 2, 3), (T, 1, 4, 5), (T, 0, 6, 7), (T, 1, 8, 9)] * 3)
     for group in (3, 4):
-        opt = q.make_options(tile_bits=10, group_bits=group)
+        opt = q.make_options(lazy_qubits=-1, tile_bits=10, group_bits=group)
         passes, nops = q.qsim_plan(10, q.QSIM_C128, gates, opt)
         assert [p["fused"] for p in passes] == [1] and passes[0]["n_ops"] == nops == 12
 
@@ -127,7 +127,8 @@ def test_toffoli_run_whose_controls_cover_the_tile():
 ])
 def test_pass_flops_count_each_operations_2x2(gate, sigma, per_amp, controls):
     M = 10
-    passes, nops = q.qsim_plan(M, q.QSIM_C64, cg.gates_from_list([gate]), sigma=sigma, seed=3)
+    passes, nops = q.qsim_plan(M, q.QSIM_C64, cg.gates_from_list([gate]),
+                               q.make_options(lazy_qubits=-1), sigma=sigma, seed=3)
     assert nops == 1 and len(passes) == 1
     assert passes[0]["flops"] == per_amp * 2.0 ** (M - controls)
 

@@ -89,14 +89,14 @@ def test_order_keeps_every_non_commuting_pair(M, seed):
     gates = cg.random_circuit(M, 200, seed, kinds=(cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT, cg.TOFFOLI,
                                                      cg.CPHASE))
     em = oracle.Errors(sigma=0.01, p_bitflip=0.01, p_phaseflip=0.01, seed=seed, trial=5)
-    _check(M, gates, em, None)
+    _check(M, gates, em, q.make_options(lazy_qubits=-1))
 
 
 def test_tiles_hold_the_targets_at_full_tile_size():
     M = 24
     gates = cg.random_circuit(M, 300, 8)
     em = oracle.Errors(sigma=1e-3, p_bitflip=1e-3, p_phaseflip=1e-3, seed=8, trial=0)
-    passes, _, _ = _check(M, gates, em, None)
+    passes, _, _ = _check(M, gates, em, q.make_options(lazy_qubits=-1))
     assert all(p["fused"] and bin(p["tile_mask"]).count("1") == 13 for p in passes)
 
 
@@ -105,7 +105,7 @@ def test_norm_follows_the_pass_that_completes_each_boundary(mode):
     M = 16
     gates = cg.random_circuit(M, 256, 11)
     em = oracle.Errors(sigma=0.0, p_bitflip=0.005, p_phaseflip=0.005, seed=11, trial=2)
-    passes, _, _ = _check(M, gates, em, q.make_options(renorm_period=16, exec_mode=mode),
+    passes, _, _ = _check(M, gates, em, q.make_options(lazy_qubits=-1, renorm_period=16, exec_mode=mode),
                           period=16)
     assert 1 <= sum(p["norm_after"] for p in passes) <= 256 // 16
 
@@ -113,10 +113,10 @@ def test_norm_follows_the_pass_that_completes_each_boundary(mode):
 def test_in_order_mode_runs_the_stream_as_is():
     M = 20
     gates = cg.random_circuit(M, 300, 12)
-    passes, nops, order = q.qsim_plan(M, q.QSIM_C64, gates, q.make_options(exec_mode=2),
+    passes, nops, order = q.qsim_plan(M, q.QSIM_C64, gates, q.make_options(lazy_qubits=-1, exec_mode=2),
                                       return_order=True)
     assert np.array_equal(order, np.arange(nops))
-    plain, _, order1 = q.qsim_plan(M, q.QSIM_C64, gates, q.make_options(exec_mode=1),
+    plain, _, order1 = q.qsim_plan(M, q.QSIM_C64, gates, q.make_options(lazy_qubits=-1, exec_mode=1),
                                    return_order=True)
     assert np.array_equal(order1, np.arange(nops)) and len(plain) == nops
 
@@ -125,8 +125,8 @@ def test_reordering_cuts_the_passes_of_a_uniform_random_circuit():
     # targets uniform over 30 qubits: commuting gates from further down the
     # stream fill each tile, so a third fewer passes than runs of the stream
     gates = cg.random_circuit(30, 1000, 30)
-    reord, _ = q.qsim_plan(30, q.QSIM_C64, gates)
-    inorder, _ = q.qsim_plan(30, q.QSIM_C64, gates, q.make_options(exec_mode=2))
+    reord, _ = q.qsim_plan(30, q.QSIM_C64, gates, q.make_options(lazy_qubits=-1))
+    inorder, _ = q.qsim_plan(30, q.QSIM_C64, gates, q.make_options(lazy_qubits=-1, exec_mode=2))
     assert all(p["fused"] for p in reord + inorder)
     assert len(reord) * 1.3 < len(inorder)
     assert 1000 / len(reord) > 20
