@@ -357,6 +357,16 @@ typedef struct {
                                    64 GiB and 80% of the free device memory */
     int strict_fifo;            /* 1: admit in arrival order only; 0: a request
                                    that fits may pass a waiting one that does not */
+    int max_heavy;              /* heavy requests (see heavy_bytes) in flight at
+                                   once, >= 0; 0: 1.  One register pass of a heavy
+                                   request already streams HBM at full rate, so a
+                                   second one would only share the bandwidth and
+                                   stretch both; light requests fill the other
+                                   slots (with strict_fifo a heavy request that
+                                   must wait holds back everything behind it) */
+    size_t heavy_bytes;         /* footprint (both registers) from which a request
+                                   is heavy; 0: 256 MiB, i.e. registers that no
+                                   longer fit the GPU's 256 MB last-level cache */
 } qsim_serve_options;
 
 /* Serve reqs[0..n) and write out[0..n) (same order).  Blocks until every

@@ -90,6 +90,7 @@ def lib() -> ctypes.CDLL:
                                     ctypes.c_uint64, dp]
         L.oq_run_trials.restype = ctypes.c_int
         L.oq_num_threads.restype = ctypes.c_int
+        L.oq_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -211,6 +212,12 @@ def run_trials(gates, M, errors: Errors, n_trials: int) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().oq_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the pair loops from now on (timing only; results do not
+    depend on it)."""
+    lib().oq_set_num_threads(int(n))
 
 
 def as_complex(psi: np.ndarray) -> np.ndarray:

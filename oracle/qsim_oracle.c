@@ -460,3 +460,15 @@ int oq_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the OpenMP pair loops from now on (n >= 1); used to time the
+ * oracle on one core beside all of them.  The results do not depend on it. */
+void oq_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

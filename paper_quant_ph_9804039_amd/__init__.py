@@ -93,7 +93,8 @@ class qsim_result(ctypes.Structure):
 
 class qsim_serve_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("max_slots", ctypes.c_int),
-                ("hbm_budget", ctypes.c_size_t), ("strict_fifo", ctypes.c_int)]
+                ("hbm_budget", ctypes.c_size_t), ("strict_fifo", ctypes.c_int),
+                ("max_heavy", ctypes.c_int), ("heavy_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -343,7 +344,7 @@ def qsim_trial_plan(gates, num_qubits: int, group_bits: int) -> np.ndarray:
 
 
 def qsim_serve(requests, max_slots: int = 8, hbm_budget: int = 0, strict_fifo: bool = False,
-               device: int = 0):
+               device: int = 0, max_heavy: int = 0, heavy_bytes: int = 0):
     """Serve a list of requests (dicts with keys M, dtype, gates, sigma,
     p_bitflip, p_phaseflip, seed, trial, arrival_s) with continuous batching;
     returns one result dict per request (fidelity, admit_s, done_s, status,
@@ -359,7 +360,8 @@ def qsim_serve(requests, max_slots: int = 8, hbm_budget: int = 0, strict_fifo: b
                                   r.get("p_phaseflip", 0.0), r.get("seed", 0), r.get("trial", 0)),
                               float(r.get("arrival_s", 0.0)))
     out = (qsim_result * max(1, n))()
-    opt = qsim_serve_options(device, max_slots, hbm_budget, 1 if strict_fifo else 0)
+    opt = qsim_serve_options(device, max_slots, hbm_budget, 1 if strict_fifo else 0, max_heavy,
+                             heavy_bytes)
     _check(lib().qsim_serve(arr, n, ctypes.byref(opt), out))
     return [{f: getattr(out[i], f) for f, _ in qsim_result._fields_} for i in range(n)]
 

@@ -1,10 +1,13 @@
 // qsim_serve: continuous batching of simulation requests on one GPU.
 //
 // One host thread runs an event loop: arrivals join a waiting list; a waiting
-// request is admitted when a slot (HIP stream) is idle and the arena has room
-// for its two registers; admission queues all of its work on the slot's
-// stream (error-free run, noisy run, fidelity, a copy of four doubles into
-// pinned memory, an event), so admitted requests overlap on the device; the
+// request is admitted when a slot (HIP stream) is idle, the arena has room
+// for its two registers and, if its registers stream from HBM ("heavy"),
+// fewer than max_heavy heavy requests are in flight (a heavy request alone
+// keeps the HBM busy; light ones overlap with it almost for free); admission
+// queues all of its work on the slot's stream (error-free run, noisy run,
+// fidelity, a copy of four doubles into pinned memory, an event), so
+// admitted requests overlap on the device; the
 // loop polls the events and, when one completes, takes the fidelity and
 // returns slot and memory.  The arena is one allocation made before the
 // loop, split first-fit; registers are bound to slot states whose scratch
@@ -158,6 +161,10 @@ extern "C" int qsim_serve(const qsim_request *reqs, size_t n, const qsim_serve_o
         const int nslots = o.max_slots == 0 ? 8 : o.max_slots;
         if (nslots < 1 || nslots > 64)
             return set_error(QSIM_EINVAL, "max_slots %d outside [1, 64]", o.max_slots);
+        if (o.max_heavy < 0)
+            return set_error(QSIM_EINVAL, "max_heavy %d is negative", o.max_heavy);
+        const int max_heavy = o.max_heavy == 0 ? 1 : o.max_heavy;
+        const size_t heavy_bytes = o.heavy_bytes == 0 ? ((size_t)256 << 20) : o.heavy_bytes;
         int max_m = 1;
         char why[160];
         for (size_t i = 0; i < n; ++i) {
@@ -259,7 +266,12 @@ extern "C" int qsim_serve(const qsim_request *reqs, size_t n, const qsim_serve_o
                 ++finished;
                 progress = true;
             }
-            // admissions, in arrival order
+            // admissions, in arrival order; at most max_heavy heavy requests
+            // in flight
+            int heavy_now = 0;
+            for (const Slot &s : L.slots)
+                if (s.busy && s.bytes >= heavy_bytes)
+                    ++heavy_now;
             for (auto it = waiting.begin(); it != waiting.end();) {
                 auto free_slot = std::find_if(L.slots.begin(), L.slots.end(),
                                               [](const Slot &s) { return !s.busy; });
@@ -268,6 +280,13 @@ extern "C" int qsim_serve(const qsim_request *reqs, size_t n, const qsim_serve_o
                 const size_t i = *it;
                 size_t off = 0;
                 const size_t bytes = footprint(reqs[i]);
+                const bool heavy = bytes >= heavy_bytes;
+                if (heavy && heavy_now >= max_heavy) {
+                    if (o.strict_fifo)
+                        break;
+                    ++it;
+                    continue;
+                }
                 if (!arena.alloc(bytes, off)) {
                     if (o.strict_fifo)
                         break;
@@ -289,6 +308,8 @@ extern "C" int qsim_serve(const qsim_request *reqs, size_t n, const qsim_serve_o
                     ++finished;
                 } else {
                     sl.busy = true;
+                    if (heavy)
+                        ++heavy_now;
                 }
                 it = waiting.erase(it);
                 progress = true;

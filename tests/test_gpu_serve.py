@@ -97,3 +97,25 @@ def test_serve_rejects_malformed_requests():
     with pytest.raises(q.QsimError):
         q.qsim_serve(reqs, max_slots=100)
     assert q.qsim_serve([]) == []
+
+
+def test_heavy_requests_never_share_the_device():
+    """With at most one heavy request in flight (registers of at least
+    heavy_bytes), no two heavy requests overlap in time, light ones still
+    overlap with them, and every result is the one it gets alone."""
+    reqs = _requests(30, 4600, m_range=(10, 18), g_range=(100, 300))
+    heavy_bytes = 2 * 8 * (1 << 15)  # M >= 15 is heavy
+    res = q.qsim_serve(reqs, max_slots=6, max_heavy=1, heavy_bytes=heavy_bytes)
+    assert all(x["status"] == 0 for x in res)
+    heavy = [(x["admit_s"], x["done_s"]) for r, x in zip(reqs, res) if _footprint(r) >= heavy_bytes]
+    light = [(x["admit_s"], x["done_s"]) for r, x in zip(reqs, res) if _footprint(r) < heavy_bytes]
+    assert len(heavy) >= 5 and len(light) >= 5
+    for i, (a0, a1) in enumerate(heavy):
+        for b0, b1 in heavy[i + 1:]:
+            assert a1 <= b0 or b1 <= a0
+    assert any(a0 < b1 and b0 < a1 for a0, a1 in heavy for b0, b1 in light)
+    seq = q.qsim_serve([dict(r, arrival_s=0.0) for r in reqs], max_slots=1, strict_fifo=True)
+    for x, y in zip(res, seq):
+        assert x["fidelity"] == y["fidelity"]
+    with pytest.raises(q.QsimError):
+        q.qsim_serve(reqs[:2], max_heavy=-1)
