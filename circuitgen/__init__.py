@@ -150,6 +150,102 @@ def qft_circuit(qubits, swaps: bool = True) -> np.ndarray:
     return gates_from_list(items)
 
 
+def modexp_circuit(base: int, modulus: int, a_qubits: int):
+    """f(A) = base^A mod modulus for a general modulus (Sec. 2.2, EQ 1 and
+    Fig. 6), from X, CNOT and Toffoli gates, with A (a_qubits qubits) put in
+    uniform superposition by Hadamards first.  Returns (gates, layout).
+
+    Repeated squaring (EQ 1): bit l of A multiplies the running product P
+    (L = bits of modulus - 1, starts at 1) by m = base^(2^l) mod modulus.
+    As in Fig. 6, a multiplication is a sequence of modulo additions, one
+    per bit j of P, of the constant m 2^j mod modulus into a running sum S,
+    each controlled by bit l of A and bit j of P (their AND is formed in one
+    qubit by a Toffoli).  A modulo addition of a constant c < modulus into
+    S < modulus (S has L + 1 bits, the top one taking the sign) is: add c,
+    subtract the modulus, copy the sign into a flag, add the modulus back
+    where the flag is set, subtract c, clear the flag from the sign of that
+    result, add c again.  Additions of constants load the constant into a
+    register B (one CNOT per set bit, from the control) and run a ripple-
+    carry adder S += B built from MAJ / UMA blocks (Cuccaro et al., 2004)
+    with one carry qubit; a subtraction is the adder run backwards.  Where
+    bit l of A is 0 the multiplication copies P into S instead; P and S are
+    then swapped, and S is cleared by running, backwards, the multiplication
+    by the inverse of m.  On every basis input |A>|1>|0..0> the circuit
+    leaves |A>|base^A mod modulus>|0..0>.
+
+    Layout (qubits in order): A, P (L), S (L + 1), B (L + 1), the adder's
+    carry qubit, the flag, the AND qubit: a_qubits + 3L + 5 qubits.  This is
+    not the paper's own 4L + 4-qubit circuit (unpublished), but the same
+    function by the same decomposition."""
+    base, modulus, a_qubits = int(base), int(modulus), int(a_qubits)
+    if modulus < 3 or not (0 < base < modulus) or np.gcd(base, modulus) != 1 or a_qubits < 1:
+        raise ValueError("modexp_circuit needs 0 < base < modulus, gcd(base, modulus) = 1")
+    L = (modulus - 1).bit_length()
+    n = L + 1
+    A = list(range(a_qubits))
+    P = list(range(a_qubits, a_qubits + L))
+    S = list(range(P[-1] + 1, P[-1] + 1 + n))
+    B = list(range(S[-1] + 1, S[-1] + 1 + n))
+    carry, flag, both = B[-1] + 1, B[-1] + 2, B[-1] + 3
+    items = []
+
+    def adder():  # S += B (mod 2^n)
+        prev = [carry] + B[:-1]
+        for i in range(n):  # MAJ(prev, S_i, B_i)
+            items.extend([(CNOT, S[i], B[i]), (CNOT, prev[i], B[i]), (TOFFOLI, B[i], prev[i], S[i])])
+        for i in reversed(range(n)):  # UMA(prev, S_i, B_i)
+            items.extend([(TOFFOLI, B[i], prev[i], S[i]), (CNOT, prev[i], B[i]), (CNOT, S[i], prev[i])])
+
+    def backwards(emit):
+        start = len(items)
+        emit()
+        seg = items[start:]
+        del items[start:]
+        items.extend(reversed(seg))
+
+    def load(value, ctrl):  # B ^= value, under ctrl (None: unconditional)
+        for i in range(n):
+            if (value >> i) & 1:
+                items.append((CNOT, B[i], ctrl) if ctrl is not None else (X, B[i]))
+
+    def add_const(value, ctrl, sign):
+        load(value, ctrl)
+        adder() if sign > 0 else backwards(adder)
+        load(value, ctrl)
+
+    def mod_add(c):  # S = S + c mod modulus, where `both` is set
+        add_const(c, both, +1)
+        add_const(modulus, None, -1)
+        items.append((CNOT, flag, S[-1]))
+        add_const(modulus, flag, +1)
+        add_const(c, both, -1)
+        items.extend([(X, S[-1]), (CNOT, flag, S[-1]), (X, S[-1])])
+        add_const(c, both, +1)
+
+    def multiply(m, a_bit):  # S = a_bit ? m P mod modulus : P   (S = 0 before)
+        for j in range(L):
+            items.append((TOFFOLI, both, a_bit, P[j]))
+            mod_add((m << j) % modulus)
+            items.append((TOFFOLI, both, a_bit, P[j]))
+        items.append((X, a_bit))
+        for j in range(L):
+            items.append((TOFFOLI, S[j], a_bit, P[j]))
+        items.append((X, a_bit))
+
+    items.extend((H, q) for q in A)
+    items.append((X, P[0]))
+    for l in range(a_qubits):
+        m = pow(base, 1 << l, modulus)
+        multiply(m, A[l])
+        for j in range(L):  # swap P and S
+            items.extend([(CNOT, S[j], P[j]), (CNOT, P[j], S[j]), (CNOT, S[j], P[j])])
+        minv = pow(m, -1, modulus)
+        backwards(lambda: multiply(minv, A[l]))
+    layout = {"A": A, "P": P, "S": S, "B": B, "carry": carry, "flag": flag, "and": both,
+              "num_qubits": both + 1}
+    return gates_from_list(items), layout
+
+
 def save_gates(path, gates: np.ndarray) -> None:
     np.ascontiguousarray(gates, dtype=GATE_DTYPE).tofile(path)
 

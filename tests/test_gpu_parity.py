@@ -477,3 +477,39 @@ def test_cphase_echo_and_trials_reject_it():
     with pytest.raises(q.QsimError) as e:
         q.qsim_run_trials(gates, M, q.QSIM_C64, 1e-3, 0.0, 0.0, 1, 0, 4)
     assert e.value.code == q.QSIM_EINVAL
+
+
+# ------------------------------------------- f(A) = X^A mod N (general N)
+
+@pytest.mark.parametrize("dtype,tol", [(q.QSIM_C128, 1e-13), (q.QSIM_C64, 1e-6)])
+def test_general_modexp_distribution_and_period(dtype, tol):
+    """X = 7, N = 15, 4 bits of A (Sec. 2.2, EQ 1, Fig. 6 as modulo
+    additions, 21 qubits, ~5900 X / CNOT / Toffoli gates): every |A> holds
+    |7^A mod 15> with every scratch qubit back at 0, and the quantum FFT on A
+    then shows Fig. 4's period of four."""
+    gates, lay = cg.modexp_circuit(7, 15, 4)
+    M, a = lay["num_qubits"], 4
+    print(f"general modexp M={M} dtype={dtype}", flush=True)
+    with state(M, dtype) as s:
+        s.apply(gates)
+        p = s.probs((1 << (a + 4)) - 1)  # A and P; the rest must be 0
+        want = np.zeros(1 << (a + 4))
+        for A in range(1 << a):
+            want[A | (pow(7, A, 15) << a)] = 1.0 / (1 << a)
+        assert np.max(np.abs(p - want)) < tol
+        assert abs(s.norm() - 1.0) < 10 * tol
+        s.apply(cg.qft_circuit(range(a)))
+        pA = s.probs((1 << a) - 1)
+        wantA = np.zeros(1 << a)
+        wantA[::4] = 0.25
+        assert np.max(np.abs(pA - wantA)) < tol
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_general_modexp_with_errors_vs_oracle(mode):
+    """X = 2, N = 15, 3 bits of A (20 qubits, ~4300 gates) with angle errors
+    and flips, complex128, against the oracle element by element."""
+    gates, lay = cg.modexp_circuit(2, 15, 3)
+    M = lay["num_qubits"]
+    em = oracle.Errors(sigma=2e-3, p_bitflip=2e-5, p_phaseflip=2e-5, seed=215, trial=1)
+    _check_vs_oracle(M, gates, q.QSIM_C128, mode, em, tol_amp=1e-12, tol_f=1e-12)
