@@ -239,14 +239,18 @@ def bench_mc(q, cg, np):
 def bench_large(q, cg, np):
     """Large registers (64 GiB): M=33 complex64 and M=32 complex128, a
     500-gate circuit with half of the targets on the top 4 qubits, sigma =
-    1e-3.  Fused-pass HBM rate of each, and the complex64 register's error
-    against the complex128 one at M=33 (192 GiB on the device at once)."""
+    1e-3.  Fused-pass HBM rate of each, with the automatic qubit remap (the
+    most used top qubits exchanged with low ones for the call) and without
+    it, and the complex64 register's error against the complex128 one at
+    M=33 (192 GiB on the device at once)."""
     out = {"gates": 500, "top_bias": 0.5, "sigma": SIGMA}
     full = q.make_options(lazy_qubits=-1)
-    for Ml, dt, name in ((33, q.QSIM_C64, "m33_c64"), (32, q.QSIM_C128, "m32_c128")):
+    runs = ((33, q.QSIM_C64, "m33_c64", 0), (33, q.QSIM_C64, "m33_c64_no_remap", -1),
+            (32, q.QSIM_C128, "m32_c128", 0), (32, q.QSIM_C128, "m32_c128_no_remap", -1))
+    for Ml, dt, name, remap in runs:
         gates = cg.random_circuit(Ml, 500, Ml, top_bias=0.5)
         try:
-            with q.State(Ml, dt, full) as s:
+            with q.State(Ml, dt, q.make_options(lazy_qubits=-1, remap_qubits=remap)) as s:
                 s.inject_errors(SIGMA, 0.0, 0.0, seed=1000 + Ml, trial=0)
                 s.apply(gates[:20])
                 s.synchronize()
@@ -261,6 +265,7 @@ def bench_large(q, cg, np):
             continue
         gbs = st["fused_bytes"] / (st["fused_ms"] * 1e-3) / 1e9 if st["fused_ms"] > 0 else None
         out[name] = {"amplitude_updates_per_s": 500 * float(1 << Ml) / wall,
+                     "remapped_qubit_pairs": st["remaps"],
                      "fused_passes": st["fused_passes"], "fused_GBps": gbs,
                      "hbm_frac": gbs / HBM_PEAK_GBS if gbs else None,
                      "avg_fused_ms": st["fused_ms"] / max(1, st["fused_passes"]),

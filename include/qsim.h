@@ -126,6 +126,18 @@ typedef struct {
                             the dynamically allocated state vector, Sec. 3.2).
                             -1: every pass streams the whole register.  The
                             per-operation path (exec_mode 1) never skips. */
+    int remap_qubits;    /* 0 (default): on registers of 31 qubits or more, a
+                            call whose operations use some of the top 6
+                            qubits far more often than the low qubits just
+                            above the always-tiled ones first exchanges up to
+                            4 such pairs (exact swaps), runs on the exchanged
+                            positions and exchanges them back at its end, so
+                            that its tiles read nearby memory (the one-GPU
+                            form of the reorganisation of Sec. 3.1, 3.3 and
+                            Fig. 8); the layout between calls never changes.
+                            1: the same on every register size whenever a
+                            top qubit is used more than twice as often as
+                            its partner.  -1: never. */
 } qsim_options;
 
 /* Per-state counters of the work launched since the last reset of the
@@ -144,6 +156,8 @@ typedef struct {
     double other_ms;         /* reductions, init, scaling */
     double fused_flops;      /* algorithmic real flops of the fused launches
                                 (see qsim_pass_info.flops) */
+    uint64_t remaps;         /* qubit pairs exchanged by remaps (each pair: one
+                                exchange at a call's start, one at its end) */
 } qsim_stats;
 
 /* Allocate a register of num_qubits (1..QSIM_MAX_QUBITS) in `dtype` and set it
@@ -375,6 +389,78 @@ typedef struct {
  * ENOMEM if the budget cannot be allocated. */
 int qsim_serve(const qsim_request *reqs, size_t n, const qsim_serve_options *opt,
                qsim_result *out);
+
+/* ------------------------------------------------------ three-state model
+ *
+ * The paper's detailed model (Sec. 2.0): each ion of the Cirac-Zoller trap
+ * has its two QU-bit levels plus a temporary third level that the
+ * controlled-not gate passes through, so M ions take 3^M states (Sec. 3.0)
+ * and one laser transformation is 3^(M-1) independent operations on the
+ * pairs of states that differ only in the transformed ion's level (Sec.
+ * 3.1).  State index i = sum_q d_q 3^q with d_q in {0, 1, 2} the level of
+ * ion q.  Gates are lowered to transformations (five for a CNOT, Sec. 2.0);
+ * every transformation's angle deviates by eps = sigma z (Sec. 1.4); after
+ * each gate the decoherence flips act on the QU-bit levels (a bit flip
+ * exchanges levels 0 and 1, a phase flip negates level 1).
+ *
+ * Transformation on ion `ion` between levels a < b: kind 0 (rotation) is
+ * exp(-i theta/2 (e^{i phi}|a><b| + e^{-i phi}|b><a|)), kind 1 (phase)
+ * multiplies levels a and b by e^{-i theta/2} and e^{+i theta/2}; the third
+ * level is untouched.  With cond_ion >= 0 it acts only on the states whose
+ * ion cond_ion is in level cond_level.  Lowering (the paper gives no pulse
+ * sequences; this is the library's reading): X = rot(01, pi, 0); H =
+ * rot(01, pi/2, -pi/2), rot(01, pi, 0); Rz(t) = phase(01, t); Z =
+ * phase(01, pi); CNOT(c, x) = rot_x(01, pi/2, pi/2), rot_c(12, pi, 0),
+ * [c in 2] rot_x(12, 2 pi, 0), rot_c(12, pi, pi), rot_x(01, pi/2, -pi/2)
+ * (exactly CNOT on the QU-bit levels); CPHASE(t) = phase_c(t/2),
+ * phase_x(t/2), CNOT, phase_x(-t/2), CNOT; Toffoli = the six-CNOT circuit
+ * with H on the target and phases of +-pi/4 (both up to a global phase).
+ * The angle error of a gate's k-th transformation uses Philox4x64-10 at
+ * counter (step, k, 3, 0), Box-Muller on the high halves of words 0 and 1;
+ * the flips use the two-state model's draws. */
+typedef struct qsim3_state qsim3_state; /* opaque, owned by the library */
+
+typedef struct {
+    uint32_t kind;       /* 0 rotation, 1 phase */
+    int32_t ion;
+    int32_t a, b;        /* levels, 0 <= a < b <= 2 */
+    int32_t cond_ion;    /* -1: unconditional */
+    int32_t cond_level;
+    double theta, phi;
+} qsim3_pulse;
+
+/* Register of num_ions (1..20) ions in dtype, set to |0...0>; the options
+ * used are device and hip_stream.  EINVAL / ENOMEM as qsim_create. */
+int qsim3_create(int num_ions, int dtype, const qsim_options *opt, qsim3_state **out);
+int qsim3_destroy(qsim3_state *s);
+/* Basis state |basis_index> (0 <= basis_index < 3^M), step counter 0. */
+int qsim3_reset(qsim3_state *s, uint64_t basis_index);
+/* Arm (copied) or disarm (NULL) the error model, as qsim_inject_errors. */
+int qsim3_inject_errors(qsim3_state *s, const qsim_error_model *em);
+/* Lower gates[0..n) and apply their transformations in order, each gate
+ * followed by its step's flips (Sec. 2.0, 3.4).  Asynchronous.  EINVAL for
+ * a bad gate (nothing applied). */
+int qsim3_apply_circuit(qsim3_state *s, const qsim_gate *gates, size_t n);
+/* Apply transformations directly (no angle errors, no step).  EINVAL for a
+ * malformed one (nothing applied). */
+int qsim3_apply_pulses(qsim3_state *s, const qsim3_pulse *p, size_t n);
+/* Host-only: the transformations gates[0..n) lower to; min(cap, count)
+ * written to out (may be NULL), the count to *n_pulses. */
+int qsim3_lower(const qsim_gate *gates, size_t n, int num_ions, qsim3_pulse *out, size_t cap,
+                size_t *n_pulses);
+/* {re <a|b>, im <a|b>, <a|a>, <b|b>} in FP64, fixed reduction order. */
+int qsim3_overlap(const qsim3_state *a, const qsim3_state *b, double out[4]);
+/* F = |<a|b>|^2 / (<a|a><b|b>) (the library's fidelity, see qsim_fidelity). */
+int qsim3_fidelity(const qsim3_state *a, const qsim3_state *b, double *out_F);
+/* Marginal probabilities of the ions in ion_mask (at most 6): out_len =
+ * 3^m, entry k spells their levels in ascending ion order as base-3 digits. */
+int qsim3_probs(const qsim3_state *s, uint64_t ion_mask, double *out, size_t out_len);
+/* Amplitudes [offset, offset + count) as interleaved FP64 re/im pairs. */
+int qsim3_get_amplitudes(const qsim3_state *s, uint64_t offset, uint64_t count, double *out);
+int qsim3_synchronize(qsim3_state *s);
+/* Register size, dtype, step counter and transformations applied. */
+int qsim3_info(const qsim3_state *s, int *num_ions, int *dtype, uint64_t *step,
+               uint64_t *transformations);
 
 /* Wait for all work queued on the state's stream. */
 int qsim_synchronize(qsim_state *s);

@@ -22,16 +22,19 @@ from circuitgen import GATE_DTYPE
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qsim_oracle.c")
+_SRC3 = os.path.join(_HERE, "qtrit_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (FP contraction off, OpenMP pair loops)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
+        os.path.getmtime(_SRC), os.path.getmtime(_SRC3))
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-fopenmp", "-Wall", "-o", tmp, _SRC, "-lm"]
+               "-fno-fast-math", "-fopenmp", "-Wall", "-o", tmp, _SRC, _SRC3, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -222,3 +225,89 @@ def set_num_threads(n: int) -> None:
 
 def as_complex(psi: np.ndarray) -> np.ndarray:
     return psi[0::2] + 1j * psi[1::2]
+
+
+# ------------------------------------------------------- three-state model
+
+class _Pulse3(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("ion", ctypes.c_int32), ("a", ctypes.c_int32),
+                ("b", ctypes.c_int32), ("cond_ion", ctypes.c_int32),
+                ("cond_level", ctypes.c_int32), ("theta", ctypes.c_double),
+                ("phi", ctypes.c_double)]
+
+
+PULSE_ROT, PULSE_PHASE = 0, 1
+
+
+def _lib3():
+    L = lib()
+    if not hasattr(L, "_q3_ready"):
+        dp = ctypes.POINTER(ctypes.c_double)
+        ep = ctypes.POINTER(_Errors)
+        pp = ctypes.POINTER(_Pulse3)
+        L.oq3_lower_gate.argtypes = [ctypes.c_void_p, pp, ctypes.c_size_t]
+        L.oq3_lower_gate.restype = ctypes.c_size_t
+        L.oq3_pulse_matrix.argtypes = [pp, ctypes.c_double, dp]
+        L.oq3_apply_pulse.argtypes = [dp, ctypes.c_int, pp, ctypes.c_double]
+        L.oq3_init.argtypes = [dp, ctypes.c_int, ctypes.c_uint64]
+        L.oq3_run.argtypes = [dp, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ep,
+                              ctypes.c_uint64]
+        L.oq3_run.restype = ctypes.c_int
+        L.oq3_probs.argtypes = [dp, ctypes.c_int, ctypes.c_uint64, dp]
+        L._q3_ready = True
+    return L
+
+
+def _pulse(p) -> _Pulse3:
+    return _Pulse3(int(p["kind"]), int(p["ion"]), int(p.get("a", 0)), int(p.get("b", 1)),
+                   int(p.get("cond_ion", -1)), int(p.get("cond_level", 0)),
+                   float(p.get("theta", 0.0)), float(p.get("phi", 0.0)))
+
+
+def lower3(gate) -> list:
+    """The three-state model's transformations of one gate (list of dicts)."""
+    g = np.ascontiguousarray(np.array([gate], dtype=GATE_DTYPE))
+    buf = (_Pulse3 * 64)()
+    n = _lib3().oq3_lower_gate(g.ctypes.data, buf, 64)
+    return [{f: getattr(buf[i], f) for f, _ in _Pulse3._fields_} for i in range(n)]
+
+
+def pulse_matrix3(pulse, eps: float = 0.0) -> np.ndarray:
+    u = np.zeros(8)
+    p = _pulse(pulse)
+    _lib3().oq3_pulse_matrix(ctypes.byref(p), eps, _dp(u))
+    return (u[0::2] + 1j * u[1::2]).reshape(2, 2)
+
+
+def init3(M: int, k: int = 0) -> np.ndarray:
+    psi = np.empty(2 * 3 ** M, dtype=np.float64)
+    _lib3().oq3_init(_dp(psi), M, k)
+    return psi
+
+
+def apply_pulse3(psi, M, pulse, eps: float = 0.0):
+    p = _pulse(pulse)
+    _lib3().oq3_apply_pulse(_dp(psi), M, ctypes.byref(p), eps)
+    return psi
+
+
+def run3(psi, M, gates, errors: Errors | None = None, step0: int = 0):
+    g = _gates(gates)
+    e = errors._c() if errors is not None else None
+    rc = _lib3().oq3_run(_dp(psi), M, g.ctypes.data, len(g),
+                         ctypes.byref(e) if e is not None else None, step0)
+    if rc != 0:
+        raise ValueError("three-state oracle rejected the circuit or error model")
+    return psi
+
+
+def simulate3(M: int, gates, errors: Errors | None = None, k: int = 0) -> np.ndarray:
+    return run3(init3(M, k), M, gates, errors)
+
+
+def probs3(psi, M, mask=None) -> np.ndarray:
+    if mask is None:
+        mask = (1 << M) - 1
+    out = np.zeros(3 ** bin(mask).count("1"))
+    _lib3().oq3_probs(_dp(psi), M, mask, _dp(out))
+    return out

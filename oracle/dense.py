@@ -107,3 +107,34 @@ def simulate(M: int, gates, errors=None, k: int = 0, step0: int = 0) -> np.ndarr
             if phase:
                 psi = full_matrix(M, PAULI_Z, q) @ psi
     return psi
+
+
+# ------------------------------------------------------- three-state model
+
+def pulse_matrix3_dense(M: int, pulse, eps: float = 0.0) -> np.ndarray:
+    """3^M x 3^M matrix of one transformation of the three-state model, built
+    from its generator: expm(-i (theta+eps)/2 (e^{i phi}|a><b| + h.c.)) on
+    the ion's three levels (a phase transformation: expm(-i (theta+eps)/2
+    (|a><a| - |b><b|))), Kronecker products over the ions (ion q has place
+    value 3^q, so the leftmost factor is ion M-1), and a projector onto the
+    condition ion's level when the transformation is conditional."""
+    th = float(pulse["theta"]) + eps
+    Gm = np.zeros((3, 3), dtype=complex)
+    a, b = int(pulse.get("a", 0)), int(pulse.get("b", 1))
+    if int(pulse["kind"]) == 1:
+        Gm[a, a], Gm[b, b] = 1.0, -1.0
+    else:
+        ph = float(pulse["phi"])
+        Gm[a, b] = np.exp(1j * ph)
+        Gm[b, a] = np.exp(-1j * ph)
+    U3 = scipy.linalg.expm(-0.5j * th * Gm)
+    I3 = np.eye(3, dtype=complex)
+    ion = int(pulse["ion"])
+    K = _kron_all([U3 if q == ion else I3 for q in reversed(range(M))])
+    ci = int(pulse.get("cond_ion", -1))
+    if ci < 0:
+        return K
+    Pv = np.zeros((3, 3), dtype=complex)
+    Pv[int(pulse["cond_level"]), int(pulse["cond_level"])] = 1.0
+    P = _kron_all([Pv if q == ci else I3 for q in reversed(range(M))])
+    return (np.eye(3 ** M, dtype=complex) - P) + P @ K

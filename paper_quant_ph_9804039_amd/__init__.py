@@ -34,6 +34,9 @@ EXPORTED = [
     "qsim_get_amplitudes", "qsim_set_amplitudes", "qsim_run_trials", "qsim_synchronize",
     "qsim_info", "qsim_profile", "qsim_get_stats", "qsim_last_error", "qsim_plan", "qsim_serve",
     "qsim_trial_plan", "qsim_overlap_noalloc", "qsim_touched_qubits",
+    "qsim3_create", "qsim3_destroy", "qsim3_reset", "qsim3_inject_errors", "qsim3_apply_circuit",
+    "qsim3_apply_pulses", "qsim3_lower", "qsim3_overlap", "qsim3_fidelity", "qsim3_probs",
+    "qsim3_get_amplitudes", "qsim3_synchronize", "qsim3_info",
 ]
 
 
@@ -54,7 +57,8 @@ class qsim_options(ctypes.Structure):
                 ("ext_buffer", ctypes.c_void_p), ("ext_bytes", ctypes.c_size_t),
                 ("renorm_period", ctypes.c_int), ("exec_mode", ctypes.c_int),
                 ("tile_bits", ctypes.c_int), ("low_bits", ctypes.c_int),
-                ("group_bits", ctypes.c_int), ("lazy_qubits", ctypes.c_int)]
+                ("group_bits", ctypes.c_int), ("lazy_qubits", ctypes.c_int),
+                ("remap_qubits", ctypes.c_int)]
 
 
 class qsim_stats(ctypes.Structure):
@@ -63,7 +67,7 @@ class qsim_stats(ctypes.Structure):
                 ("renorms", ctypes.c_uint64), ("pass_ms", ctypes.c_double),
                 ("pass_bytes", ctypes.c_double), ("fused_ms", ctypes.c_double),
                 ("fused_bytes", ctypes.c_double), ("other_ms", ctypes.c_double),
-                ("fused_flops", ctypes.c_double)]
+                ("fused_flops", ctypes.c_double), ("remaps", ctypes.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -75,6 +79,16 @@ class qsim_pass_info(ctypes.Structure):
                 ("norm_after", ctypes.c_uint32), ("span_qubits", ctypes.c_uint32),
                 ("tile_mask", ctypes.c_uint64), ("flops", ctypes.c_double),
                 ("tiles", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class qsim3_pulse(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("ion", ctypes.c_int32), ("a", ctypes.c_int32),
+                ("b", ctypes.c_int32), ("cond_ion", ctypes.c_int32),
+                ("cond_level", ctypes.c_int32), ("theta", ctypes.c_double),
+                ("phi", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -140,6 +154,20 @@ def lib() -> ctypes.CDLL:
         "qsim_overlap_noalloc": [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  vp, dp],
         "qsim_touched_qubits": [vp, ctypes.POINTER(u64)],
+        "qsim3_create": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(qsim_options), ctypes.POINTER(vp)],
+        "qsim3_destroy": [vp],
+        "qsim3_reset": [vp, u64],
+        "qsim3_inject_errors": [vp, ctypes.POINTER(qsim_error_model)],
+        "qsim3_apply_circuit": [vp, vp, sz],
+        "qsim3_apply_pulses": [vp, ctypes.POINTER(qsim3_pulse), sz],
+        "qsim3_lower": [vp, sz, ctypes.c_int, ctypes.POINTER(qsim3_pulse), sz, ctypes.POINTER(sz)],
+        "qsim3_overlap": [vp, vp, dp],
+        "qsim3_fidelity": [vp, vp, dp],
+        "qsim3_probs": [vp, u64, dp, sz],
+        "qsim3_get_amplitudes": [vp, u64, u64, dp],
+        "qsim3_synchronize": [vp],
+        "qsim3_info": [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                       ctypes.POINTER(u64), ctypes.POINTER(u64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -374,9 +402,9 @@ def qsim_last_error() -> str:
 
 def make_options(device=0, hip_stream=None, ext_buffer=None, ext_bytes=0, renorm_period=0,
                  exec_mode=0, tile_bits=0, low_bits=0, group_bits=0,
-                 lazy_qubits=0) -> qsim_options:
+                 lazy_qubits=0, remap_qubits=0) -> qsim_options:
     return qsim_options(device, hip_stream, ext_buffer, ext_bytes, renorm_period, exec_mode,
-                        tile_bits, low_bits, group_bits, lazy_qubits)
+                        tile_bits, low_bits, group_bits, lazy_qubits, remap_qubits)
 
 
 def torch_options(tensor=None, stream=None, **kw) -> qsim_options:
@@ -468,3 +496,106 @@ class State:
 
     def stats(self) -> dict:
         return qsim_get_stats(self.h)
+
+
+# ------------------------------------------------------ three-state model
+
+def qsim3_lower(gates, num_ions: int) -> list:
+    """Host-only: the transformations of the three-state model the gates
+    lower to, as dicts."""
+    g = _gates(gates)
+    n = ctypes.c_size_t()
+    L = lib()
+    _check(L.qsim3_lower(g.ctypes.data, len(g), num_ions, None, 0, ctypes.byref(n)))
+    out = (qsim3_pulse * max(1, n.value))()
+    _check(L.qsim3_lower(g.ctypes.data, len(g), num_ions, out, n.value, ctypes.byref(n)))
+    return [out[i].as_dict() for i in range(n.value)]
+
+
+class State3:
+    """Owning wrapper of one three-state register (3^M amplitudes)."""
+
+    def __init__(self, num_ions: int, dtype: int = QSIM_C64, options: qsim_options | None = None):
+        self.num_ions = num_ions
+        self._opt = options
+        h = ctypes.c_void_p()
+        _check(lib().qsim3_create(num_ions, dtype, ctypes.byref(options) if options else None,
+                                  ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h is not None:
+            _check(lib().qsim3_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def reset(self, basis_index: int = 0):
+        _check(lib().qsim3_reset(self.h, basis_index))
+        return self
+
+    def inject_errors(self, sigma=None, p_bitflip=0.0, p_phaseflip=0.0, seed=0, trial=0):
+        if sigma is None:
+            _check(lib().qsim3_inject_errors(self.h, None))
+        else:
+            em = _em(sigma, p_bitflip, p_phaseflip, seed, trial)
+            _check(lib().qsim3_inject_errors(self.h, ctypes.byref(em)))
+        return self
+
+    def apply(self, gates):
+        g = _gates(gates)
+        _check(lib().qsim3_apply_circuit(self.h, g.ctypes.data, len(g)))
+        return self
+
+    def apply_pulses(self, pulses):
+        arr = (qsim3_pulse * max(1, len(pulses)))()
+        for i, p in enumerate(pulses):
+            arr[i] = qsim3_pulse(int(p["kind"]), int(p["ion"]), int(p.get("a", 0)),
+                                 int(p.get("b", 1)), int(p.get("cond_ion", -1)),
+                                 int(p.get("cond_level", 0)), float(p.get("theta", 0.0)),
+                                 float(p.get("phi", 0.0)))
+        _check(lib().qsim3_apply_pulses(self.h, arr, len(pulses)))
+        return self
+
+    def overlap(self, other: "State3"):
+        out = np.zeros(4)
+        _check(lib().qsim3_overlap(self.h, other.h, _dp(out)))
+        return complex(out[0], out[1]), float(out[2]), float(out[3])
+
+    def fidelity(self, other: "State3") -> float:
+        out = ctypes.c_double()
+        _check(lib().qsim3_fidelity(self.h, other.h, ctypes.byref(out)))
+        return out.value
+
+    def probs(self, ion_mask: int) -> np.ndarray:
+        out = np.zeros(3 ** bin(ion_mask).count("1"))
+        _check(lib().qsim3_probs(self.h, ion_mask, _dp(out), len(out)))
+        return out
+
+    def amplitudes(self, offset: int = 0, count: int | None = None) -> np.ndarray:
+        if count is None:
+            count = 3 ** self.num_ions - offset
+        out = np.zeros(2 * count)
+        _check(lib().qsim3_get_amplitudes(self.h, offset, count, _dp(out)))
+        return out[0::2] + 1j * out[1::2]
+
+    def synchronize(self):
+        _check(lib().qsim3_synchronize(self.h))
+        return self
+
+    def info(self) -> dict:
+        M, dt, step, nt = ctypes.c_int(), ctypes.c_int(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().qsim3_info(self.h, ctypes.byref(M), ctypes.byref(dt), ctypes.byref(step),
+                                ctypes.byref(nt)))
+        return {"num_ions": M.value, "dtype": dt.value, "step": step.value,
+                "transformations": nt.value}

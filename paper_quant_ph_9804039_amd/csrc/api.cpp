@@ -89,6 +89,7 @@ struct qsim_state {
     int renorm_period = 0;   // 0 = never
     int exec_mode = 0;
     bool lazy = false;       // fused passes visit the touched qubits only
+    int remap = 0;           // qubit remap: 0 automatic, 1 eager, -1 never
     uint64_t active = 0;     // touched qubits: amplitudes spread over both values
     uint64_t fixed = 0;      // the value of every untouched qubit
     int tile_bits = 13;
@@ -1098,14 +1099,109 @@ bool tile_args_consistent(const TileArgs<R> &A, int G, const std::vector<Op> &op
     return true;
 }
 
+// ------------------------------------------------------------ qubit remap
+//
+// The one-GPU form of the paper's reorganisation of the state (Sec. 3.1,
+// Sec. 3.3 and Fig. 8: work on a chosen set of qubits, move the data when
+// the set must change, and do that rarely).  A fused pass reads each tile as
+// runs of 2^low contiguous amplitudes; a tile that spans the top qubits of a
+// large register gathers its runs from addresses 2^(M-1) elements apart,
+// which the memory system serves more slowly (at M = 33 the same pass runs
+// about a tenth faster once those qubits are low).  When a call's operations
+// use a few top qubits much more often than the low ones just above the
+// always-tiled qubits, the call exchanges each such pair first (an exact
+// swap: three CNOT exchanges, fused into the first pass like any other
+// operation), applies every operation to the exchanged positions, and
+// exchanges them back at its end, so between calls the register keeps its
+// plain layout and every readout is unchanged.
+constexpr int kRemapMinQubits = 31;  // automatic remap from this register size
+constexpr int kRemapWindow = 6;      // top qubits that may move, low ones that may take them
+constexpr int kRemapPairs = 4;
+
+void choose_remap(const qsim_state *s, const std::vector<Op> &ops,
+                  std::vector<std::pair<int, int>> &pairs)
+{
+    pairs.clear();
+    int k, G;
+    if (s->remap < 0 || s->exec_mode == 1 || !tile_shape(s, k, G))
+        return;
+    const int M = s->M, low = std::min(s->low_bits, k);
+    if ((s->remap == 0 && M < kRemapMinQubits) || M - low < 2 * kRemapWindow)
+        return;
+    int uses[64] = {0};
+    for (const Op &op : ops)
+        if (needs_tile_target(op))
+            ++uses[op.target];
+    std::vector<int> hot, cold;
+    for (int i = 0; i < kRemapWindow; ++i) {
+        hot.push_back(M - 1 - i);
+        cold.push_back(low + i);
+    }
+    std::stable_sort(hot.begin(), hot.end(), [&](int a, int b) { return uses[a] > uses[b]; });
+    std::stable_sort(cold.begin(), cold.end(), [&](int a, int b) { return uses[a] < uses[b]; });
+    // automatic: a top qubit must carry at least 1/50 of the operations (8 at
+    // least) and twice its partner's count plus that margin
+    const int margin = s->remap > 0 ? 1 : std::max(8, (int)(ops.size() / 50));
+    for (int i = 0; i < kRemapPairs; ++i)
+        if (uses[hot[i]] >= margin && uses[hot[i]] >= 2 * uses[cold[i]] + margin)
+            pairs.push_back({hot[i], cold[i]});
+}
+
+void apply_remap(const std::vector<std::pair<int, int>> &pairs, std::vector<Op> &stream)
+{
+    if (pairs.empty())
+        return;
+    int perm[64];
+    for (int q = 0; q < 64; ++q)
+        perm[q] = q;
+    for (const auto &pr : pairs) {
+        perm[pr.first] = pr.second;
+        perm[pr.second] = pr.first;
+    }
+    auto move_mask = [&](uint64_t m) {
+        uint64_t r = 0;
+        for (; m != 0; m &= m - 1)
+            r |= 1ull << perm[__builtin_ctzll(m)];
+        return r;
+    };
+    const uint64_t step0 = stream.empty() ? 0 : stream.front().step;
+    const uint64_t step1 = stream.empty() ? 0 : stream.back().step;
+    auto exchange = [&](std::vector<Op> &out, uint64_t step) {
+        for (const auto &pr : pairs) {
+            const int a = pr.first, b = pr.second;
+            const int seq[3][2] = {{b, a}, {a, b}, {b, a}};  // (target, control)
+            for (const auto &tc : seq) {
+                Op x = exact_swap(tc[0], step);
+                x.cmask = 1ull << tc[1];
+                out.push_back(x);
+            }
+        }
+    };
+    std::vector<Op> out;
+    out.reserve(stream.size() + 6 * pairs.size());
+    exchange(out, step0);
+    for (Op op : stream) {
+        op.target = perm[op.target];
+        op.cmask = move_mask(op.cmask);
+        out.push_back(op);
+    }
+    exchange(out, step1);
+    stream.swap(out);
+}
+
 // A call's operation stream made ready for scheduling: renormalisation
-// boundaries marked, then (lazy states) rewritten against the untouched
-// qubits.
-void prepare_stream(const qsim_state *s, std::vector<Op> &stream)
+// boundaries marked, the qubit remap chosen and applied, then (lazy states)
+// the stream rewritten against the untouched qubits.  Returns the number of
+// exchanged qubit pairs.
+int prepare_stream(const qsim_state *s, std::vector<Op> &stream)
 {
     mark_norms(s, stream);
+    std::vector<std::pair<int, int>> pairs;
+    choose_remap(s, stream, pairs);
+    apply_remap(pairs, stream);
     if (s->lazy)
         lazy_rewrite(s, stream);
+    return (int)pairs.size();
 }
 
 // Touched qubits and untouched values after a pass has run.
@@ -1122,7 +1218,7 @@ void track_pass(const std::vector<Op> &ops, const PassPlan &p, uint64_t &act, ui
 template <typename R>
 int run_ops(qsim_state *s, std::vector<Op> &stream)
 {
-    prepare_stream(s, stream);
+    s->stats.remaps += (uint64_t)prepare_stream(s, stream);
     std::vector<PassPlan> plan;
     std::vector<uint32_t> order;
     schedule(s, stream, order, plan);
@@ -1156,8 +1252,8 @@ int run_ops(qsim_state *s, std::vector<Op> &stream)
             s->stats.fused_passes++;
             if (p.norm_after) {
                 Timed t2(s, 2, 0);
-                HIP_TRY(launch_finish_norm(s->d_tile_norm, 1ull << (A.mact - A.k), norm_sum,
-                                           s->stream), "norm launch");
+                HIP_TRY(launch_finish_norm(s->d_tile_norm, 1ull << (A.mact - A.k), s->d_partial,
+                                           norm_sum, s->stream), "norm launch");
                 t2.done();
                 scale_pending = true;
                 s->stats.renorms++;
@@ -1176,7 +1272,7 @@ int run_ops(qsim_state *s, std::vector<Op> &stream)
             if (p.norm_after) {
                 Timed t2(s, 2, full / 2);
                 HIP_TRY(launch_norm<R>(psi, s->M, s->d_partial, s->d_scalars, s->stream), "norm");
-                HIP_TRY(launch_finish_norm(s->d_scalars + 2, 1, norm_sum, s->stream), "norm");
+                HIP_TRY(launch_finish_norm(s->d_scalars + 2, 1, nullptr, norm_sum, s->stream), "norm");
                 t2.done();
                 scale_pending = true;
                 s->stats.renorms++;
@@ -1233,6 +1329,8 @@ int configure(qsim_state *s, int num_qubits, int dtype, const qsim_options &o)
         return fail(QSIM_EINVAL, "renorm_period %d", o.renorm_period);
     if (o.lazy_qubits < -1 || o.lazy_qubits > 1)
         return fail(QSIM_EINVAL, "lazy_qubits %d is not -1, 0 or 1", o.lazy_qubits);
+    if (o.remap_qubits < -1 || o.remap_qubits > 1)
+        return fail(QSIM_EINVAL, "remap_qubits %d is not -1, 0 or 1", o.remap_qubits);
     const size_t eb = elem_bytes(dtype);
     const size_t bytes = ((size_t)1 << num_qubits) * eb;
     if (o.ext_buffer && o.ext_bytes < bytes)
@@ -1264,6 +1362,7 @@ int configure(qsim_state *s, int num_qubits, int dtype, const qsim_options &o)
     s->bytes = bytes;
     // the per-operation path always streams the whole register
     s->lazy = o.lazy_qubits >= 0 && o.exec_mode != 1;
+    s->remap = o.remap_qubits;
     s->active = s->lazy ? 0 : full_mask(num_qubits);
     s->fixed = 0;  // the register starts (or is rebound) at |0...0>
     return QSIM_OK;

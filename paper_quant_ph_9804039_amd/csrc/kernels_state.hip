@@ -289,6 +289,22 @@ __global__ void __launch_bounds__(kBlock) k_reduce_finish(const double *partial,
     }
 }
 
+// First stage of a long sum: block b adds values [b chunk, (b + 1) chunk) in
+// the fixed order of block_sum.
+__global__ void __launch_bounds__(kBlock) k_sum_chunks(const double *values, uint64_t n,
+                                                       uint64_t chunk, double *partial)
+{
+    __shared__ double scratch[1][kBlock / 64];
+    double v[1] = {0.0};
+    const uint64_t lo = (uint64_t)blockIdx.x * chunk;
+    const uint64_t hi = lo + chunk < n ? lo + chunk : n;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock)
+        v[0] += values[i];
+    block_sum<1>(v, scratch);
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = v[0];
+}
+
 __global__ void __launch_bounds__(kBlock) k_finish_norm(const double *tile_norms, uint64_t n,
                                                         double *out)
 {
@@ -510,9 +526,24 @@ hipError_t launch_norm(const cplx<R> *a, int M, double *partial, double *out, hi
     return hipGetLastError();
 }
 
-hipError_t launch_finish_norm(const double *tile_norms, uint64_t n, double *out, hipStream_t st)
+hipError_t launch_finish_norm(const double *tile_norms, uint64_t n, double *partial, double *out,
+                              hipStream_t st)
 {
-    hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(kBlock), 0, st, tile_norms, n, out);
+    // one block for short sums; past 16 values per thread, a first stage of
+    // up to kReduceBlocks blocks over contiguous chunks (a fixed partition of
+    // [0, n), so the result does not depend on timing)
+    constexpr uint64_t kOneBlock = 16 * (uint64_t)kBlock;
+    if (n <= kOneBlock || partial == nullptr) {
+        hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(kBlock), 0, st, tile_norms, n, out);
+        return hipGetLastError();
+    }
+    uint64_t chunk = kOneBlock;
+    while ((n + chunk - 1) / chunk > (uint64_t)kReduceBlocks)
+        chunk *= 2;
+    const uint64_t g = (n + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)g), dim3(kBlock), 0, st, tile_norms, n, chunk,
+                       partial);
+    hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(kBlock), 0, st, partial, g, out);
     return hipGetLastError();
 }
 

@@ -47,8 +47,11 @@ hipError_t launch_overlap(const cplx<Ra> *a, const cplx<Rb> *b, int M, double *p
 // out[0] = <a|a>; partial as above.
 template <typename R>
 hipError_t launch_norm(const cplx<R> *a, int M, double *partial, double *out, hipStream_t st);
-// Sum n per-tile partial norms in order; out[0] = sum, out[1] = 1/sqrt(sum).
-hipError_t launch_finish_norm(const double *tile_norms, uint64_t n, double *out, hipStream_t st);
+// Sum n per-tile partial norms in a fixed order; out[0] = sum, out[1] =
+// 1/sqrt(sum).  Long sums take a first stage over chunks whose sums land in
+// partial (kReduceBlocks doubles; may be NULL for n <= 16 * 256).
+hipError_t launch_finish_norm(const double *tile_norms, uint64_t n, double *partial, double *out,
+                              hipStream_t st);
 
 // Probabilities.  full: out[i] = |a_i|^2.  Marginal: chunk partials, then
 // out[k] summed in chunk order; `partial` holds (2^M / chunk) doubles.

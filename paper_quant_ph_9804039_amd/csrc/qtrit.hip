@@ -1,0 +1,818 @@
+// The detailed three-state model on gfx950: every ion of the Cirac-Zoller
+// trap has the two levels of its QU-bit plus the temporary third level the
+// controlled-not gate passes through (Sec. 2.0), so M ions take 3^M states
+// (Sec. 3.0) and one laser transformation is 3^(M-1) independent operations
+// on the pairs of states that differ only in the transformed ion's level
+// (Sec. 3.1).  State index i = sum_q d_q 3^q, d_q the level of ion q.
+//
+// The host lowers each gate to transformations (five for a CNOT), draws
+// their angle errors and the step's flips, and launches one kernel per
+// transformation; a launch reads and writes the two levels a, b of one ion,
+// i.e. 2/3 of the register.
+//
+// Readings of the paper (its pulse sequences are not given):
+//   - transformation on ion q between levels a < b, angle theta, phase phi:
+//     exp(-i theta/2 (e^{i phi}|a><b| + e^{-i phi}|b><a|)), third level
+//     untouched; a phase transformation multiplies levels a, b by
+//     e^{-i theta/2}, e^{+i theta/2} (on levels 0, 1 the two-state Rz);
+//   - a transformation may be conditional on another ion being in a given
+//     level (the step the trap carries through its motional mode);
+//   - X = rot(01, pi, 0); H = rot(01, pi/2, -pi/2) then rot(01, pi, 0);
+//     Rz(t) = phase(t); Z = phase(pi); CNOT(c, x) = rot_x(01, pi/2, pi/2),
+//     rot_c(12, pi, 0), [c in 2] rot_x(12, 2 pi, 0), rot_c(12, pi, pi),
+//     rot_x(01, pi/2, -pi/2); CPHASE(t) on (c, x) = phase_c(t/2),
+//     phase_x(t/2), CNOT, phase_x(-t/2), CNOT; Toffoli = the six-CNOT
+//     circuit with H on the target and phases of +-pi/4;
+//   - every transformation's angle deviates by eps = sigma z, z from
+//     Philox4x64-10 keyed by (seed, trial) at counter (step, k, 3, 0) for the
+//     gate's k-th transformation (Box-Muller on the high halves of words 0
+//     and 1); after each gate, per ion, a bit flip exchanges levels 0 and 1
+//     and a phase flip negates level 1 (counter (step, q, 2, 0)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "internal.h"
+#include "qsim.h"
+
+namespace {
+
+using qsim::cplx;
+
+constexpr int kBlock3 = 256;
+constexpr int kMaxIons = 20;      // 3^20 < 2^32: indices stay 32-bit
+constexpr int kReduceBlocks3 = 1024;
+constexpr int kMaxMarginalIons = 6;  // 3^6 = 729 bins per block in LDS
+
+uint64_t pow3(int e)
+{
+    uint64_t p = 1;
+    for (int i = 0; i < e; ++i)
+        p *= 3;
+    return p;
+}
+
+dim3 grid3(uint64_t work)
+{
+    uint64_t g = (work + kBlock3 - 1) / kBlock3;
+    g = std::min<uint64_t>(std::max<uint64_t>(g, 1), 1u << 20);
+    return dim3((unsigned)g);
+}
+
+// n / d for 32-bit n with d given with its reciprocal: the FP64 product is
+// off by at most one, which the remainder corrects.
+__device__ __forceinline__ uint32_t div_by(uint32_t n, uint32_t d, double inv)
+{
+    uint32_t q = (uint32_t)((double)n * inv);
+    const int64_t r = (int64_t)n - (int64_t)q * (int64_t)d;
+    if (r < 0)
+        --q;
+    else if (r >= (int64_t)d)
+        ++q;
+    return q;
+}
+
+// What a launch does to the pairs (level a, level b) of its ion.
+enum PairMode : uint32_t { kPairMat = 0, kPairSwap = 1, kPairNegB = 2 };
+
+template <typename R>
+struct RotArgs {
+    cplx<R> *psi;
+    uint32_t work;          // 3^(M-1) pairs
+    uint32_t place;         // 3^ion
+    double inv_place;
+    uint32_t a, b;          // levels, a < b
+    uint32_t cplace;        // 3^cond_ion (0: unconditional)
+    double inv_cplace;
+    uint32_t clevel;
+    uint32_t mode;          // PairMode
+    cplx<R> u[4];           // u00 u01 u10 u11
+};
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock3) k3_pairs(RotArgs<R> A)
+{
+    const uint32_t stride = gridDim.x * kBlock3;
+    for (uint32_t w = blockIdx.x * kBlock3 + threadIdx.x; w < A.work; w += stride) {
+        const uint32_t hi = div_by(w, A.place, A.inv_place);
+        const uint32_t lo = w - hi * A.place;
+        const uint32_t i = hi * 3u * A.place + A.a * A.place + lo;
+        if (A.cplace != 0) {
+            const uint32_t qd = div_by(i, A.cplace, A.inv_cplace);
+            if (qd - 3u * (qd / 3u) != A.clevel)
+                continue;
+        }
+        const uint32_t j = i + (A.b - A.a) * A.place;
+        const cplx<R> x = A.psi[i], y = A.psi[j];
+        if (A.mode == kPairSwap) {
+            A.psi[i] = y;
+            A.psi[j] = x;
+        } else if (A.mode == kPairNegB) {
+            A.psi[j] = {-y.re, -y.im};
+        } else {
+            A.psi[i] = qsim::cmad2(A.u[0], x, A.u[1], y);
+            A.psi[j] = qsim::cmad2(A.u[2], x, A.u[3], y);
+        }
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock3) k3_init(cplx<R> *psi, uint32_t n, uint32_t k)
+{
+    const uint32_t stride = gridDim.x * kBlock3;
+    for (uint32_t i = blockIdx.x * kBlock3 + threadIdx.x; i < n; i += stride)
+        psi[i] = {R(i == k ? 1 : 0), R(0)};
+}
+
+__device__ __forceinline__ double wave_sum3(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Fixed-order block sums of NV values (lanes, then waves in order).
+template <int NV>
+__device__ __forceinline__ void block_sum3(double (&v)[NV], double (*scratch)[kBlock3 / 64])
+{
+#pragma unroll
+    for (int c = 0; c < NV; ++c)
+        v[c] = wave_sum3(v[c]);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c)
+            scratch[c][threadIdx.x >> 6] = v[c];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock3 / 64; ++w)
+                s += scratch[c][w];
+            v[c] = s;
+        }
+    }
+}
+
+// <a|b>, <a|a>, <b|b>: block b sums elements [b chunk, (b + 1) chunk).
+template <typename Ra, typename Rb>
+__global__ void __launch_bounds__(kBlock3) k3_overlap(const cplx<Ra> *a, const cplx<Rb> *b,
+                                                      uint32_t n, uint32_t chunk, double *partial)
+{
+    __shared__ double scratch[4][kBlock3 / 64];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const uint32_t lo = blockIdx.x * chunk, hi = std::min(n, lo + chunk);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kBlock3) {
+        const double ar = a[i].re, ai = a[i].im, br = b[i].re, bi = b[i].im;
+        v[0] += ar * br + ai * bi;
+        v[1] += ar * bi - ai * br;
+        v[2] += ar * ar + ai * ai;
+        v[3] += br * br + bi * bi;
+    }
+    block_sum3<4>(v, scratch);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c)
+            partial[4 * blockIdx.x + c] = v[c];
+}
+
+__global__ void __launch_bounds__(kBlock3) k3_finish(const double *partial, uint32_t nblocks,
+                                                     uint32_t width, double *out)
+{
+    // out[c] = sum over blocks of partial[width * blk + c], c < width, in
+    // block order (one thread per entry)
+    for (uint32_t c = threadIdx.x; c < width; c += kBlock3) {
+        double s = 0.0;
+        for (uint32_t blk = 0; blk < nblocks; ++blk)
+            s += partial[(uint64_t)width * blk + c];
+        out[c] = s;
+    }
+}
+
+// Marginal probabilities over up to six ions: block b bins elements
+// [b chunk, (b + 1) chunk) into LDS, thread by thread in a fixed order, and
+// writes its 3^m bins.
+template <typename R>
+__global__ void __launch_bounds__(kBlock3) k3_marginal(const cplx<R> *psi, uint32_t n,
+                                                       uint32_t chunk, uint32_t m,
+                                                       const uint32_t *places, double *partial)
+{
+    __shared__ double bins[729];
+    __shared__ double tbins[kBlock3];
+    __shared__ uint32_t keys[kBlock3];
+    uint32_t nb = 1;
+    for (uint32_t j = 0; j < m; ++j)
+        nb *= 3;
+    for (uint32_t c = threadIdx.x; c < nb; c += kBlock3)
+        bins[c] = 0.0;
+    __syncthreads();
+    const uint32_t lo = blockIdx.x * chunk, hi = std::min(n, lo + chunk);
+    // each pass: every thread takes one element, then thread 0 adds them in
+    // thread order (deterministic, no atomics)
+    for (uint32_t base = lo; base < hi; base += kBlock3) {
+        const uint32_t i = base + threadIdx.x;
+        uint32_t key = 0;
+        double p = 0.0;
+        if (i < hi) {
+            p = (double)psi[i].re * psi[i].re + (double)psi[i].im * psi[i].im;
+            uint32_t kp = 1;
+            for (uint32_t j = 0; j < m; ++j) {
+                const uint32_t d = (i / places[j]) % 3u;
+                key += d * kp;
+                kp *= 3;
+            }
+        }
+        tbins[threadIdx.x] = p;
+        keys[threadIdx.x] = key;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int t = 0; t < kBlock3 && base + t < hi; ++t)
+                bins[keys[t]] += tbins[t];
+        __syncthreads();
+    }
+    for (uint32_t c = threadIdx.x; c < nb; c += kBlock3)
+        partial[(uint64_t)nb * blockIdx.x + c] = bins[c];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock3) k3_to_f64(const cplx<R> *psi, uint32_t count,
+                                                     double *out)
+{
+    const uint32_t stride = gridDim.x * kBlock3;
+    for (uint32_t i = blockIdx.x * kBlock3 + threadIdx.x; i < count; i += stride) {
+        out[2 * i] = psi[i].re;
+        out[2 * i + 1] = psi[i].im;
+    }
+}
+
+// ---------------------------------------------------------------- lowering
+
+enum : uint32_t { kPulseRot = 0, kPulsePhase = 1 };
+constexpr double kPi = 3.14159265358979323846;
+
+struct Lowering {
+    std::vector<qsim3_pulse> out;
+    void rot(int ion, int a, int b, double th, double ph, int cion = -1, int clev = 0)
+    {
+        out.push_back({kPulseRot, ion, a, b, cion, clev, th, ph});
+    }
+    void phase(int ion, double th) { out.push_back({kPulsePhase, ion, 0, 1, -1, 0, th, 0.0}); }
+    void cnot(int c, int x)
+    {
+        rot(x, 0, 1, kPi / 2, kPi / 2);
+        rot(c, 1, 2, kPi, 0.0);
+        rot(x, 1, 2, 2 * kPi, 0.0, c, 2);
+        rot(c, 1, 2, kPi, kPi);
+        rot(x, 0, 1, kPi / 2, -kPi / 2);
+    }
+    void h(int x)
+    {
+        rot(x, 0, 1, kPi / 2, -kPi / 2);
+        rot(x, 0, 1, kPi, 0.0);
+    }
+    void gate(const qsim_gate &g)
+    {
+        const int x = g.target, c0 = g.ctrl0, c1 = g.ctrl1;
+        switch (g.kind) {
+        case QSIM_X: rot(x, 0, 1, kPi, 0.0); break;
+        case QSIM_H: h(x); break;
+        case QSIM_RZ: phase(x, g.theta); break;
+        case QSIM_Z: phase(x, kPi); break;
+        case QSIM_CNOT: cnot(c0, x); break;
+        case QSIM_CPHASE:
+            phase(c0, 0.5 * g.theta);
+            phase(x, 0.5 * g.theta);
+            cnot(c0, x);
+            phase(x, -0.5 * g.theta);
+            cnot(c0, x);
+            break;
+        default:  // Toffoli
+            h(x);
+            cnot(c1, x); phase(x, -kPi / 4);
+            cnot(c0, x); phase(x, kPi / 4);
+            cnot(c1, x); phase(x, -kPi / 4);
+            cnot(c0, x); phase(c1, kPi / 4); phase(x, kPi / 4);
+            h(x);
+            cnot(c0, c1); phase(c0, kPi / 4); phase(c1, -kPi / 4);
+            cnot(c0, c1);
+            break;
+        }
+    }
+};
+
+// 2x2 of a transformation with its angle error, FP64, as u00 u01 u10 u11.
+void pulse_matrix(const qsim3_pulse &p, double eps, double (&u)[8])
+{
+    const double th = p.theta + eps, c = std::cos(0.5 * th), s = std::sin(0.5 * th);
+    std::memset(u, 0, sizeof(u));
+    if (p.kind == kPulsePhase) {
+        u[0] = c; u[1] = -s; u[6] = c; u[7] = s;
+        return;
+    }
+    u[0] = c;
+    u[2] = s * std::sin(p.phi); u[3] = -s * std::cos(p.phi);
+    u[4] = -s * std::sin(p.phi); u[5] = -s * std::cos(p.phi);
+    u[6] = c;
+}
+
+double pulse_eps(const qsim_error_model &em, uint64_t step, uint64_t k)
+{
+    const qsim::u64x4 r = qsim::philox4x64_10(step, k, 3, 0, em.seed, em.trial);
+    const double u1 = ((double)(r.w[0] >> 32) + 0.5) * 0x1p-32;
+    const double u2 = ((double)(r.w[1] >> 32) + 0.5) * 0x1p-32;
+    return em.sigma * std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586476925286766559 * u2);
+}
+
+bool pulse_valid(const qsim3_pulse &p, int M)
+{
+    if (p.kind > kPulsePhase || p.ion < 0 || p.ion >= M || p.a < 0 || p.b > 2 || p.a >= p.b)
+        return false;
+    if (p.cond_ion != -1 && (p.cond_ion < 0 || p.cond_ion >= M || p.cond_ion == p.ion ||
+                             p.cond_level < 0 || p.cond_level > 2))
+        return false;
+    return std::isfinite(p.theta) && std::isfinite(p.phi);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- state
+
+struct qsim3_state {
+    int M = 0;
+    int dtype = QSIM_C64;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void *psi = nullptr;
+    uint64_t n = 0;
+    uint64_t step = 0;
+    bool armed = false;
+    qsim_error_model em{};
+    double *d_partial = nullptr;   // 729 * kReduceBlocks3 doubles
+    double *d_out = nullptr;       // 729 doubles
+    uint32_t *d_places = nullptr;  // marginal ions' place values
+    double *d_stage = nullptr;
+    size_t stage_bytes = 0;
+    uint64_t pulses = 0;
+};
+
+namespace {
+
+int fail3(int code, const char *what, hipError_t e)
+{
+    (void)hipGetLastError();
+    if (e == hipErrorOutOfMemory)
+        return qsim::set_error(QSIM_ENOMEM, "%s: out of device memory", what);
+    return qsim::set_error(code, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP3(expr, what)                              \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess)                         \
+            return fail3(QSIM_EDEVICE, what, e_);     \
+    } while (0)
+
+size_t esize(int dtype) { return dtype == QSIM_C64 ? 8 : 16; }
+
+// One transformation (or exact flip) on the register.
+template <typename R>
+hipError_t launch_pairs(qsim3_state *s, int ion, int a, int b, int cion, int clev, uint32_t mode,
+                        const double (&u)[8])
+{
+    RotArgs<R> A{};
+    A.psi = static_cast<cplx<R> *>(s->psi);
+    A.work = (uint32_t)(s->n / 3);
+    A.place = (uint32_t)pow3(ion);
+    A.inv_place = 1.0 / (double)A.place;
+    A.a = (uint32_t)a;
+    A.b = (uint32_t)b;
+    A.cplace = cion >= 0 ? (uint32_t)pow3(cion) : 0u;
+    A.inv_cplace = cion >= 0 ? 1.0 / (double)A.cplace : 0.0;
+    A.clevel = (uint32_t)clev;
+    A.mode = mode;
+    for (int k = 0; k < 4; ++k)
+        A.u[k] = {(R)u[2 * k], (R)u[2 * k + 1]};
+    hipLaunchKernelGGL((k3_pairs<R>), grid3(A.work), dim3(kBlock3), 0, s->stream, A);
+    return hipGetLastError();
+}
+
+hipError_t pairs(qsim3_state *s, int ion, int a, int b, int cion, int clev, uint32_t mode,
+                 const double (&u)[8])
+{
+    return s->dtype == QSIM_C64 ? launch_pairs<float>(s, ion, a, b, cion, clev, mode, u)
+                                : launch_pairs<double>(s, ion, a, b, cion, clev, mode, u);
+}
+
+int apply_pulse(qsim3_state *s, const qsim3_pulse &p, double eps)
+{
+    double u[8];
+    pulse_matrix(p, eps, u);
+    HIP3(pairs(s, p.ion, p.a, p.b, p.cond_ion, p.cond_level, kPairMat, u), "transformation");
+    ++s->pulses;
+    return QSIM_OK;
+}
+
+void release3(qsim3_state *s)
+{
+    if (s == nullptr)
+        return;
+    (void)hipSetDevice(s->device);
+    if (s->stream)
+        (void)hipStreamSynchronize(s->stream);
+    if (s->psi)
+        (void)hipFree(s->psi);
+    if (s->d_partial)
+        (void)hipFree(s->d_partial);
+    if (s->d_out)
+        (void)hipFree(s->d_out);
+    if (s->d_places)
+        (void)hipFree(s->d_places);
+    if (s->d_stage)
+        (void)hipFree(s->d_stage);
+    if (s->own_stream && s->stream)
+        (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+int ensure_stage3(qsim3_state *s, size_t bytes)
+{
+    if (s->stage_bytes >= bytes)
+        return QSIM_OK;
+    HIP3(hipStreamSynchronize(s->stream), "stage sync");
+    if (s->d_stage)
+        (void)hipFree(s->d_stage);
+    s->d_stage = nullptr;
+    s->stage_bytes = 0;
+    HIP3(hipMalloc((void **)&s->d_stage, bytes), "stage");
+    s->stage_bytes = bytes;
+    return QSIM_OK;
+}
+
+int validate3(const qsim3_state *s, const qsim_gate *g, size_t n)
+{
+    if (n > 0 && g == nullptr)
+        return qsim::set_error(QSIM_EINVAL, "gates is NULL");
+    char why[160];
+    for (size_t k = 0; k < n; ++k)
+        if (!qsim::gate_valid(g[k], s->M, why, sizeof(why)))
+            return qsim::set_error(QSIM_EINVAL, "gate %zu: %s", k, why);
+    return QSIM_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+int qsim3_create(int num_ions, int dtype, const qsim_options *opt, qsim3_state **out)
+{
+    return qsim::guarded(__func__, [&]() -> int {
+        if (out == nullptr)
+            return qsim::set_error(QSIM_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (num_ions < 1 || num_ions > kMaxIons)
+            return qsim::set_error(QSIM_EINVAL, "num_ions %d outside [1, %d]", num_ions, kMaxIons);
+        if (dtype != QSIM_C64 && dtype != QSIM_C128)
+            return qsim::set_error(QSIM_EINVAL, "dtype %d", dtype);
+        qsim_options o{};
+        if (opt)
+            o = *opt;
+        int ndev = 0;
+        hipError_t e = hipGetDeviceCount(&ndev);
+        if (e != hipSuccess)
+            return fail3(QSIM_EDEVICE, "hipGetDeviceCount", e);
+        if (o.device < 0 || o.device >= ndev)
+            return qsim::set_error(QSIM_EINVAL, "device %d outside [0, %d)", o.device, ndev);
+        qsim3_state *s = new (std::nothrow) qsim3_state();
+        if (s == nullptr)
+            return qsim::set_error(QSIM_ENOMEM, "qsim3_create: host memory exhausted");
+        s->M = num_ions;
+        s->dtype = dtype;
+        s->device = o.device;
+        s->n = pow3(num_ions);
+        e = hipSetDevice(o.device);
+        if (e == hipSuccess) {
+            if (o.hip_stream) {
+                s->stream = static_cast<hipStream_t>(o.hip_stream);
+            } else {
+                e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+                s->own_stream = e == hipSuccess;
+            }
+        }
+        if (e == hipSuccess)
+            e = hipMalloc(&s->psi, s->n * esize(dtype));
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&s->d_partial, 729 * kReduceBlocks3 * sizeof(double));
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&s->d_out, 729 * sizeof(double));
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&s->d_places, kMaxMarginalIons * sizeof(uint32_t));
+        if (e == hipSuccess) {
+            if (dtype == QSIM_C64)
+                hipLaunchKernelGGL((k3_init<float>), grid3(s->n), dim3(kBlock3), 0, s->stream,
+                                   (cplx<float> *)s->psi, (uint32_t)s->n, 0u);
+            else
+                hipLaunchKernelGGL((k3_init<double>), grid3(s->n), dim3(kBlock3), 0, s->stream,
+                                   (cplx<double> *)s->psi, (uint32_t)s->n, 0u);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) {
+            const int rc = fail3(QSIM_EDEVICE, "qsim3_create", e);
+            release3(s);
+            return rc;
+        }
+        *out = s;
+        return QSIM_OK;
+    });
+}
+
+int qsim3_destroy(qsim3_state *s)
+{
+    return qsim::guarded(__func__, [&]() -> int {
+        release3(s);
+        return QSIM_OK;
+    });
+}
+
+int qsim3_reset(qsim3_state *s, uint64_t basis_index)
+{
+    return qsim::guarded(__func__, [&]() -> int {
+        if (s == nullptr)
+            return qsim::set_error(QSIM_EINVAL, "state is NULL");
+        if (basis_index >= s->n)
+            return qsim::set_error(QSIM_ERANGE, "basis index %llu >= 3^%d",
+                                   (unsigned long long)basis_index, s->M);
+        HIP3(hipSetDevice(s->device), "hipSetDevice");
+        if (s->dtype == QSIM_C64)
+            hipLaunchKernelGGL((k3_init<float>), grid3(s->n), dim3(kBlock3), 0, s->stream,
+                               (cplx<float> *)s->psi, (uint32_t)s->n, (uint32_t)basis_index);
+        else
+            hipLaunchKernelGGL((k3_init<double>), grid3(s->n), dim3(kBlock3), 0, s->stream,
+                               (cplx<double> *)s->psi, (uint32_t)s->n, (uint32_t)basis_index);
+        HIP3(hipGetLastError(), "init");
+        s->step = 0;
+        return QSIM_OK;
+    });
+}
+
+int qsim3_inject_errors(qsim3_state *s, const qsim_error_model *em)
+{
+    return qsim::guarded(__func__, [&]() -> int {
+        if (s == nullptr)
+            return qsim::set_error(QSIM_EINVAL, "state is NULL");
+        if (em == nullptr) {
+            s->armed = false;
+            return QSIM_OK;
+        }
+        if (!qsim::error_model_valid(*em))
+            return qsim::set_error(QSIM_EINVAL, "bad error model");
+        s->em = *em;
+        s->armed = true;
+        return QSIM_OK;
+    });
+}
+
+int qsim3_lower(const qsim_gate *gates, size_t n, int num_ions, qsim3_pulse *out, size_t cap,
+                size_t *n_pulses)
+{
+    return qsim::guarded(__func__, [&]() -> int {
+        if (num_ions < 1 || num_ions > kMaxIons)
+            return qsim::set_error(QSIM_EINVAL, "num_ions %d", num_ions);
+        qsim3_state probe;
+        probe.M = num_ions;
+        int rc = validate3(&probe, gates, n);
+        if (rc != QSIM_OK)
+            return rc;
+        Lowering L;
+        for (size_t k = 0; k < n; ++k)
+            L.gate(gates[k]);
+        if (n_pulses)
+            *n_pulses = L.out.size();
+        for (size_t i = 0; i < L.out.size() && i < cap && out != nullptr; ++i)
+            out[i] = L.out[i];
+        return QSIM_OK;
+    });
+}
+
+int qsim3_apply_circuit(qsim3_state *s, const qsim_gate *gates, size_t n)
+{
+    return qsim::guarded(__func__, [&]() -> int {
+        if (s == nullptr)
+            return qsim::set_error(QSIM_EINVAL, "state is NULL");
+        int rc = validate3(s, gates, n);
+        if (rc != QSIM_OK)
+            return rc;
+        HIP3(hipSetDevice(s->device), "hipSetDevice");
+        const bool ang = s->armed && s->em.sigma > 0.0;
+        const bool flips = s->armed && (s->em.p_bitflip > 0.0 || s->em.p_phaseflip > 0.0);
+        const uint64_t tb = flips ? qsim::flip_threshold(s->em.p_bitflip) : 0;
+        const uint64_t tp = flips ? qsim::flip_threshold(s->em.p_phaseflip) : 0;
+        const double ident[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+        for (size_t k = 0; k < n; ++k) {
+            const uint64_t step = s->step + k;
+            Lowering L;
+            L.gate(gates[k]);
+            for (size_t j = 0; j < L.out.size(); ++j) {
+                rc = apply_pulse(s, L.out[j], ang ? pulse_eps(s->em, step, j) : 0.0);
+                if (rc != QSIM_OK)
+                    return rc;
+            }
+            if (!flips)
+                continue;
+            for (int q = 0; q < s->M; ++q) {
+                const qsim::u64x4 r = qsim::philox4x64_10(step, (uint64_t)q, qsim::kStreamFlip, 0,
+                                                          s->em.seed, s->em.trial);
+                if ((r.w[0] >> 32) < tb)
+                    HIP3(pairs(s, q, 0, 1, -1, 0, kPairSwap, ident), "bit flip");
+                if ((r.w[1] >> 32) < tp)
+                    HIP3(pairs(s, q, 0, 1, -1, 0, kPairNegB, ident), "phase flip");
+            }
+        }
+        s->step += n;
+        return QSIM_OK;
+    });
+}
+
+int qsim3_apply_pulses(qsim3_state *s, const qsim3_pulse *p, size_t n)
+{
+    return qsim::guarded(__func__, [&]() -> int {
+        if (s == nullptr || (n > 0 && p == nullptr))
+            return qsim::set_error(QSIM_EINVAL, "NULL argument");
+        for (size_t k = 0; k < n; ++k)
+            if (!pulse_valid(p[k], s->M))
+                return qsim::set_error(QSIM_EINVAL, "transformation %zu is malformed", k);
+        HIP3(hipSetDevice(s->device), "hipSetDevice");
+        for (size_t k = 0; k < n; ++k) {
+            const int rc = apply_pulse(s, p[k], 0.0);
+            if (rc != QSIM_OK)
+                return rc;
+        }
+        return QSIM_OK;
+    });
+}
+
+int qsim3_overlap(const qsim3_state *a, const qsim3_state *b, double out[4])
+{
+    return qsim::guarded(__func__, [&]() -> int {
+        if (a == nullptr || b == nullptr || out == nullptr)
+            return qsim::set_error(QSIM_EINVAL, "NULL argument");
+        if (a->M != b->M || a->device != b->device)
+            return qsim::set_error(QSIM_EINVAL, "registers differ in size or device");
+        HIP3(hipSetDevice(a->device), "hipSetDevice");
+        HIP3(hipStreamSynchronize(b->stream), "sync");
+        const uint32_t n = (uint32_t)a->n;
+        uint32_t chunk = kBlock3;
+        while ((n + chunk - 1) / chunk > (uint32_t)kReduceBlocks3)
+            chunk *= 2;
+        const uint32_t g = (n + chunk - 1) / chunk;
+        hipStream_t st = a->stream;
+        if (a->dtype == QSIM_C64 && b->dtype == QSIM_C64)
+            hipLaunchKernelGGL((k3_overlap<float, float>), dim3(g), dim3(kBlock3), 0, st,
+                               (const cplx<float> *)a->psi, (const cplx<float> *)b->psi, n, chunk,
+                               a->d_partial);
+        else if (a->dtype == QSIM_C64)
+            hipLaunchKernelGGL((k3_overlap<float, double>), dim3(g), dim3(kBlock3), 0, st,
+                               (const cplx<float> *)a->psi, (const cplx<double> *)b->psi, n,
+                               chunk, a->d_partial);
+        else if (b->dtype == QSIM_C64)
+            hipLaunchKernelGGL((k3_overlap<double, float>), dim3(g), dim3(kBlock3), 0, st,
+                               (const cplx<double> *)a->psi, (const cplx<float> *)b->psi, n,
+                               chunk, a->d_partial);
+        else
+            hipLaunchKernelGGL((k3_overlap<double, double>), dim3(g), dim3(kBlock3), 0, st,
+                               (const cplx<double> *)a->psi, (const cplx<double> *)b->psi, n,
+                               chunk, a->d_partial);
+        hipLaunchKernelGGL(k3_finish, dim3(1), dim3(kBlock3), 0, st, a->d_partial, g, 4u,
+                           a->d_out);
+        HIP3(hipGetLastError(), "overlap");
+        HIP3(hipMemcpyAsync(out, a->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, st),
+             "overlap copy");
+        HIP3(hipStreamSynchronize(st), "overlap sync");
+        return QSIM_OK;
+    });
+}
+
+int qsim3_fidelity(const qsim3_state *a, const qsim3_state *b, double *out_F)
+{
+    return qsim::guarded(__func__, [&]() -> int {
+        if (out_F == nullptr)
+            return qsim::set_error(QSIM_EINVAL, "out_F is NULL");
+        double o[4];
+        const int rc = qsim3_overlap(a, b, o);
+        if (rc != QSIM_OK)
+            return rc;
+        *out_F = (o[0] * o[0] + o[1] * o[1]) / (o[2] * o[3]);
+        return QSIM_OK;
+    });
+}
+
+int qsim3_probs(const qsim3_state *s, uint64_t ion_mask, double *out, size_t out_len)
+{
+    return qsim::guarded(__func__, [&]() -> int {
+        if (s == nullptr || out == nullptr)
+            return qsim::set_error(QSIM_EINVAL, "NULL argument");
+        if (ion_mask >> s->M)
+            return qsim::set_error(QSIM_EINVAL, "mask has bits at or above ion %d", s->M);
+        const int m = __builtin_popcountll(ion_mask);
+        if (m > kMaxMarginalIons)
+            return qsim::set_error(QSIM_EINVAL, "at most %d ions per marginal", kMaxMarginalIons);
+        const uint64_t nb = pow3(m);
+        if (out_len != nb)
+            return qsim::set_error(QSIM_EINVAL, "out_len %zu != 3^%d", out_len, m);
+        qsim3_state *ms = const_cast<qsim3_state *>(s);
+        HIP3(hipSetDevice(s->device), "hipSetDevice");
+        uint32_t places[kMaxMarginalIons] = {0};
+        int j = 0;
+        for (int q = 0; q < s->M; ++q)
+            if ((ion_mask >> q) & 1u)
+                places[j++] = (uint32_t)pow3(q);
+        HIP3(hipMemcpyAsync(ms->d_places, places, sizeof(places), hipMemcpyHostToDevice,
+                            s->stream), "places");
+        const uint32_t n = (uint32_t)s->n;
+        uint32_t chunk = kBlock3;
+        while ((n + chunk - 1) / chunk > (uint32_t)kReduceBlocks3)
+            chunk *= 2;
+        const uint32_t g = (n + chunk - 1) / chunk;
+        if (s->dtype == QSIM_C64)
+            hipLaunchKernelGGL((k3_marginal<float>), dim3(g), dim3(kBlock3), 0, s->stream,
+                               (const cplx<float> *)s->psi, n, chunk, (uint32_t)m, ms->d_places,
+                               ms->d_partial);
+        else
+            hipLaunchKernelGGL((k3_marginal<double>), dim3(g), dim3(kBlock3), 0, s->stream,
+                               (const cplx<double> *)s->psi, n, chunk, (uint32_t)m, ms->d_places,
+                               ms->d_partial);
+        hipLaunchKernelGGL(k3_finish, dim3(1), dim3(kBlock3), 0, s->stream, ms->d_partial, g,
+                           (uint32_t)nb, ms->d_out);
+        HIP3(hipGetLastError(), "marginal");
+        HIP3(hipMemcpyAsync(out, ms->d_out, nb * sizeof(double), hipMemcpyDeviceToHost,
+                            s->stream), "probs copy");
+        HIP3(hipStreamSynchronize(s->stream), "probs sync");
+        return QSIM_OK;
+    });
+}
+
+int qsim3_get_amplitudes(const qsim3_state *s, uint64_t offset, uint64_t count, double *out)
+{
+    return qsim::guarded(__func__, [&]() -> int {
+        if (s == nullptr || (out == nullptr && count > 0))
+            return qsim::set_error(QSIM_EINVAL, "NULL argument");
+        if (offset > s->n || count > s->n - offset)
+            return qsim::set_error(QSIM_ERANGE, "range outside the 3^%d amplitudes", s->M);
+        if (count == 0)
+            return QSIM_OK;
+        qsim3_state *ms = const_cast<qsim3_state *>(s);
+        HIP3(hipSetDevice(s->device), "hipSetDevice");
+        const uint64_t chunk = std::min<uint64_t>(count, 1ull << 22);
+        int rc = ensure_stage3(ms, chunk * 16);
+        if (rc != QSIM_OK)
+            return rc;
+        for (uint64_t done = 0; done < count; done += chunk) {
+            const uint32_t c = (uint32_t)std::min(chunk, count - done);
+            if (s->dtype == QSIM_C64)
+                hipLaunchKernelGGL((k3_to_f64<float>), grid3(c), dim3(kBlock3), 0, s->stream,
+                                   (const cplx<float> *)s->psi + offset + done, c, ms->d_stage);
+            else
+                hipLaunchKernelGGL((k3_to_f64<double>), grid3(c), dim3(kBlock3), 0, s->stream,
+                                   (const cplx<double> *)s->psi + offset + done, c, ms->d_stage);
+            HIP3(hipGetLastError(), "convert");
+            HIP3(hipMemcpyAsync(out + 2 * done, ms->d_stage, (size_t)c * 16,
+                                hipMemcpyDeviceToHost, s->stream), "amplitude copy");
+            HIP3(hipStreamSynchronize(s->stream), "amplitude sync");
+        }
+        return QSIM_OK;
+    });
+}
+
+int qsim3_synchronize(qsim3_state *s)
+{
+    return qsim::guarded(__func__, [&]() -> int {
+        if (s == nullptr)
+            return qsim::set_error(QSIM_EINVAL, "state is NULL");
+        HIP3(hipSetDevice(s->device), "hipSetDevice");
+        HIP3(hipStreamSynchronize(s->stream), "sync");
+        return QSIM_OK;
+    });
+}
+
+int qsim3_info(const qsim3_state *s, int *num_ions, int *dtype, uint64_t *step,
+               uint64_t *transformations)
+{
+    return qsim::guarded(__func__, [&]() -> int {
+        if (s == nullptr)
+            return qsim::set_error(QSIM_EINVAL, "state is NULL");
+        if (num_ions) *num_ions = s->M;
+        if (dtype) *dtype = s->dtype;
+        if (step) *step = s->step;
+        if (transformations) *transformations = s->pulses;
+        return QSIM_OK;
+    });
+}
+
+}  // extern "C"

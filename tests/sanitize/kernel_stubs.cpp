@@ -25,7 +25,10 @@ hipError_t launch_overlap(const cplx<Ra> *, const cplx<Rb> *, int, double *, dou
 }
 template <typename R>
 hipError_t launch_norm(const cplx<R> *, int, double *, double *, hipStream_t) { return hipErrorInvalidValue; }
-hipError_t launch_finish_norm(const double *, uint64_t, double *, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_finish_norm(const double *, uint64_t, double *, double *, hipStream_t)
+{
+    return hipErrorInvalidValue;
+}
 template <typename R>
 hipError_t launch_probs_full(const cplx<R> *, int, double *, hipStream_t) { return hipErrorInvalidValue; }
 template <typename R>

@@ -21,7 +21,7 @@ HEADER = os.path.join(ROOT, "include", "qsim.h")
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(qsim_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(qsim3?_[a-z_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(libpath):
         assert hasattr(L, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", libpath], capture_output=True,
                          text=True).stdout
-    exported = set(re.findall(r" T (qsim_\w+)", out))
+    exported = set(re.findall(r" T (qsim3?_\w+)", out))
     assert set(_declared()) <= exported
     assert set(q.EXPORTED) == set(_declared())
 
@@ -60,7 +60,7 @@ def test_struct_layouts(tmp_path):
     assert "double theta;" in text and "uint32_t kind;" in text
     # every struct the binding mirrors has the size the C compiler gives it
     names = ["qsim_gate", "qsim_error_model", "qsim_options", "qsim_stats", "qsim_pass_info",
-             "qsim_request", "qsim_result", "qsim_serve_options"]
+             "qsim_request", "qsim_result", "qsim_serve_options", "qsim3_pulse"]
     src = tmp_path / "sizes.c"
     src.write_text('#include <stdio.h>\n#include "qsim.h"\nint main(void) {\n' +
                    "".join(f'printf("%zu\\n", sizeof({n}));\n' for n in names) +
