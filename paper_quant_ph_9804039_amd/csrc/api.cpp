@@ -659,6 +659,7 @@ void schedule_fused(const qsim_state *s, const std::vector<Op> &ops, size_t lo, 
                     std::vector<PassPlan> &plan)
 {
     const int low = std::min(s->low_bits, k);
+    const size_t cap = s->dtype == QSIM_C64 ? (size_t)kPassOps<float> : (size_t)kPassOps<double>;
     std::vector<uint32_t> rem, left;
     for (size_t i = lo; i < hi; ++i)
         rem.push_back((uint32_t)i);
@@ -672,7 +673,7 @@ void schedule_fused(const qsim_state *s, const std::vector<Op> &ops, size_t lo, 
         for (size_t r = 0; r < rem.size(); ++r) {
             const Op &op = ops[rem[r]];
             const OpUse u = op_use(op);
-            bool ok = taken < (size_t)kMaxPassOps && (u.x & (bx | bz)) == 0 && (u.z & bx) == 0;
+            bool ok = taken < cap && (u.x & (bx | bz)) == 0 && (u.z & bx) == 0;
             if (ok && needs_tile_target(op)) {
                 const uint64_t tb = 1ull << op.target;
                 if (!(S & tb)) {
@@ -689,7 +690,7 @@ void schedule_fused(const qsim_state *s, const std::vector<Op> &ops, size_t lo, 
                 ++taken;
                 continue;
             }
-            if (!reorder || taken == (size_t)kMaxPassOps) {
+            if (!reorder || taken == cap) {
                 left.insert(left.end(), rem.begin() + (std::ptrdiff_t)r, rem.end());
                 break;
             }
@@ -1002,7 +1003,7 @@ template <typename R>
 bool tile_args_consistent(const TileArgs<R> &A, int G, const std::vector<Op> &ops,
                           const PassPlan &p, char *why, size_t n)
 {
-    if (A.nops != p.count || A.nops == 0 || A.nops > (uint32_t)kMaxPassOps) {
+    if (A.nops != p.count || A.nops == 0 || A.nops > (uint32_t)kPassOps<R>) {
         snprintf(why, n, "op count %u", A.nops);
         return false;
     }

@@ -129,7 +129,11 @@ struct PlainArgs {
 };
 
 constexpr int kMaxTileBits = 14;
-constexpr int kMaxPassOps = 32;
+// Operations per fused pass: they travel in the kernel arguments (at most
+// 4 KiB), so complex64 passes take more than complex128 ones.
+template <typename R>
+constexpr int kPassOps = sizeof(R) == 4 ? 63 : 40;
+constexpr int kMaxPassOps = 63;
 constexpr int kMaxGroups = 32;
 constexpr uint32_t kNoPos = 0xFFu;
 constexpr int kMaxRuns = 16;  // runs of consecutive qubits in a tile set or its complement
@@ -161,12 +165,12 @@ struct TileOp {
     R c[8];             // kTPair: m00 m01 m10 m11 w0 w1; diagonal kinds: d0, d1 (re, im)
 };
 
-// Group word of a fused pass: first op (5 bits), op count (6 bits), then the
-// G <= 5 sorted tile bits of the group, 4 bits each (31 bits in all).
-constexpr uint32_t kGroupCountShift = 5;
-constexpr uint32_t kGroupBitsShift = 11;
-static_assert(kMaxPassOps <= 32 && kMaxTileBits <= 16, "group word field widths");
-__host__ __device__ inline uint32_t group_first(uint32_t w) { return w & 31u; }
+// Group word of a fused pass: first op (6 bits), op count (6 bits), then the
+// G <= 5 sorted tile bits of the group, 4 bits each (32 bits in all).
+constexpr uint32_t kGroupCountShift = 6;
+constexpr uint32_t kGroupBitsShift = 12;
+static_assert(kMaxPassOps <= 63 && kMaxTileBits <= 16, "group word field widths");
+__host__ __device__ inline uint32_t group_first(uint32_t w) { return w & 63u; }
 __host__ __device__ inline uint32_t group_count(uint32_t w) { return (w >> kGroupCountShift) & 63u; }
 __host__ __device__ inline uint32_t group_bit(uint32_t w, int i)
 {
@@ -199,9 +203,11 @@ struct TileArgs {
     uint32_t group[kMaxGroups];        // see group_first / group_count / group_bit
     R phase[2];                        // global phase of the pass's uncontrolled diagonals
     uint32_t use_phase;                // phase != 1
-    TileOp<R> ops[kMaxPassOps];
+    TileOp<R> ops[kPassOps<R>];
 };
 
-static_assert(sizeof(TileArgs<double>) <= 4096, "kernel arguments must fit 4 KiB");
+static_assert(sizeof(TileArgs<float>) <= 4096 && sizeof(TileArgs<double>) <= 4096,
+              "kernel arguments must fit 4 KiB");
+static_assert(kPassOps<float> <= kMaxPassOps && kPassOps<double> <= kMaxPassOps, "op caps");
 
 }  // namespace qsim

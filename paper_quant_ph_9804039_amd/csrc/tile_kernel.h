@@ -391,14 +391,20 @@ template <typename R, int G>
 __device__ __forceinline__ void load_quantum(const cplx<R> *p, const uint64_t (&o)[G], bool pair0,
                                              cplx<R> (&x)[1 << G])
 {
+    // the empty asm statements fence each shape in its own branch: without
+    // them the compiler hoists and merges parts of both into narrow loads
     if (pair0) {
+        __asm__ volatile("" ::: "memory");
 #pragma unroll
         for (int r = 0; r < (1 << G); r += 2)
             ld2(p + greg<G>(o, r), x[r], x[r + 1]);
+        __asm__ volatile("" ::: "memory");
     } else {
+        __asm__ volatile("" ::: "memory");
 #pragma unroll
         for (int r = 0; r < (1 << G); ++r)
             x[r] = p[greg<G>(o, r)];
+        __asm__ volatile("" ::: "memory");
     }
 }
 
@@ -443,9 +449,11 @@ constexpr int kTileWaves = (sizeof(R) == 4 && G == 4) ? 4 : 1;
 // Fused pass, persistent: each workgroup walks tiles blockIdx.x, +gridDim.x,
 // ...  Each of the T threads holds one quantum of 2^G amplitudes in
 // registers (T * 2^G = 2^k).  HBM traffic of one workgroup overlaps the
-// register and LDS work of the other workgroups on the CU (a register
-// prefetch of the next tile measured no faster and costs 2^G amplitudes of
-// registers per thread).
+// register and LDS work of the other workgroups on the CU.  Measured and not
+// kept: a register prefetch of the next tile (with or without a two-tile
+// unroll), which costs 2^G amplitudes of registers per thread and ran 5-15 %
+// slower, and an XOR swizzle of the LDS re-partition, which halved the bank
+// conflicts but added more VALU work than it saved.
 template <typename R, int G, int T>
 __global__ void __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kTileWaves<R, G>)))
 k_tile(const TileArgs<R> A)
