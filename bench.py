@@ -55,7 +55,7 @@ P_FLIP = 1e-4
 PROBS_MASK = (1 << 10) - 1
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_m30_c64_traffic.json")
 TILE_SOURCE = os.path.join(ROOT, "paper_quant_ph_9804039_amd", "csrc", "tile_kernel.h")
-SECTIONS = ("c128", "per_gate", "copy", "mc", "serving", "large", "structured")
+SECTIONS = ("c128", "per_gate", "copy", "mc", "serving", "large", "structured", "three_state")
 
 
 def log(msg: str) -> None:
@@ -279,6 +279,43 @@ def bench_large(q, cg, np):
             out["m33_c64_vs_c128"] = state_error(a, b)
     except q.QsimError as e:
         out["m33_c64_vs_c128"] = {"error": str(e)}
+    return out
+
+
+def bench_three_state(q, cg, np):
+    """The detailed three-state model (Sec. 2.0, Sec. 3.0): 19 ions, 3^19 =
+    1.16e9 complex64 amplitudes (9.3 GB), 100 random gates lowered to laser
+    transformations (a CNOT is five, through the auxiliary level) with angle
+    errors and flips.  One kernel per transformation; each rewrites the two
+    levels it couples, 2/3 of the register (1/9 when it is conditional on
+    another ion's level)."""
+    M3, G3 = 19, 100
+    gates = cg.random_circuit(M3, G3, 319, kinds=(cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT))
+    pulses = q.qsim3_lower(gates, M3)
+    eb = 8
+    pair_amps = 2 * 3 ** (M3 - 1)
+    amps = sum(pair_amps // (3 if p["cond_ion"] >= 0 else 1) for p in pulses)
+    out = {"num_ions": M3, "amplitudes": 3 ** M3, "gates": G3, "transformations": len(pulses),
+           "dtype": "c64"}
+    with q.State3(M3, q.QSIM_C64) as s:
+        s.apply(gates[:4])
+        s.synchronize()
+        walls = []
+        for r in range(2):
+            s.reset(0)
+            s.inject_errors(SIGMA, P_FLIP, P_FLIP, seed=319, trial=r)
+            s.synchronize()
+            t0 = time.perf_counter()
+            s.apply(gates)
+            s.synchronize()
+            walls.append(time.perf_counter() - t0)
+        wall = min(walls)
+        norm = float(np.sum(s.probs(1)))
+    gbps = 2 * amps * eb / wall / 1e9
+    out.update({"seconds": wall, "transformations_per_s": len(pulses) / wall,
+                "amplitude_updates_per_s": amps / wall,
+                "algorithmic_GBps": gbps, "hbm_frac": gbps / HBM_PEAK_GBS,
+                "norm_after": norm})
     return out
 
 
@@ -553,6 +590,10 @@ def main() -> int:
         log("bench: 64 GiB registers")
         extra["large_register"] = bench_large(q, cg, np)
         log(f"bench: large registers {json.dumps(extra['large_register'])}")
+    if "three_state" in sections:
+        log("bench: three-state model (19 ions)")
+        extra["three_state"] = bench_three_state(q, cg, np)
+        log(f"bench: three-state {json.dumps(extra['three_state'])}")
     if "structured" in sections:
         log("bench: structured workload (7^A mod 15 and the quantum FFT on the top qubits)")
         extra["structured_modexp15_qft"] = bench_structured(q, cg, np)

@@ -115,3 +115,52 @@ def test_bad_arguments_rejected():
         with pytest.raises(q.QsimError):
             s.probs(0b1111111)
         assert s.info()["transformations"] == 0
+
+
+def test_bench_size_register_matches_the_two_state_oracle_on_sampled_blocks():
+    """19 ions (3^19 = 1.16e9 amplitudes), the bench's gate kinds, no errors:
+    the amplitudes whose ions are all in levels 0/1 equal the two-state
+    oracle's (up to one global phase), everything with a level-2 ion is zero.
+    Checked on two contiguous blocks of 3^9 indices (ions 9..18 fixed to the
+    high bits of two of the largest two-state amplitudes)."""
+    M = 19
+    print("three-state M=19 sampled blocks", flush=True)
+    g = cg.random_circuit(M, 60, 319, kinds=(cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT))
+    ref = oracle.as_complex(oracle.simulate(M, g))
+    order = np.argsort(-np.abs(ref))
+    digits = (np.arange(3 ** 9)[:, None] // 3 ** np.arange(9)) % 3
+    binary = np.all(digits < 2, axis=1)
+    low = (digits[binary] * (1 << np.arange(9))).sum(axis=1)
+    with q.State3(M, q.QSIM_C64) as s:
+        s.apply(g)
+        phase = None
+        for top in (int(order[0]), int(order[len(order) // 8])):
+            hi = [(top >> (9 + i)) & 1 for i in range(M - 9)]
+            off = int(sum(b * 3 ** (9 + i) for i, b in enumerate(hi)))
+            blk = s.amplitudes(off, 3 ** 9)
+            want = ref[low + (top >> 9 << 9)]
+            got = blk[binary]
+            if phase is None:
+                k = int(np.argmax(np.abs(want)))
+                assert abs(want[k]) > 1e-3
+                phase = got[k] / want[k]
+            assert abs(abs(phase) - 1.0) < 1e-5
+            assert np.max(np.abs(got - phase * want)) < 2e-5
+            assert np.max(np.abs(blk[~binary])) < 2e-6
+        assert abs(float(np.sum(s.probs(1))) - 1.0) < 1e-5
+
+
+def test_largest_register_cnot_and_x_on_basis_states():
+    """20 ions (3^20 = 3.5e9 amplitudes, 28 GB complex64), the largest the
+    library takes: X and CNOT on basis states give basis states (to the
+    rounding of the pulses' cos and sin: cos(pi/2) is 6e-17 in FP64)."""
+    M = 20
+    print("three-state M=20 basis states", flush=True)
+    with q.State3(M, q.QSIM_C64) as s:
+        s.apply(cg.gates_from_list([(cg.X, 19), (cg.CNOT, 0, 19), (cg.CNOT, 10, 0),
+                                    (cg.X, 10)]))
+        want = 3 ** 19 + 3 ** 0  # ions 19, 0 in level 1; ion 10 flipped twice
+        a = s.amplitudes(want - 2, 5)
+        # each X is a pi pulse, -i X: the two of ion 10 leave a global phase
+        assert abs(abs(a[2]) - 1.0) < 1e-6 and np.max(np.abs(np.delete(a, 2))) < 1e-15
+        assert abs(float(np.sum(s.probs(1 << 19))) - 1.0) < 1e-6
