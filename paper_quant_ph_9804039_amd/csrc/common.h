@@ -188,7 +188,7 @@ struct TileArgs {
     const double *scale_in;   // if set, multiply every amplitude by *scale_in on load
     double *norm_out;         // if set, per-tile sum of |a|^2 after the pass
     uint64_t smask;           // global mask of the tile qubits
-    uint64_t emask;           // qubits the tile number enumerates (host-side checks)
+    uint64_t emask;           // qubits the tile number enumerates, = the crun runs
     uint64_t base_or;         // values of the untouched qubits outside the pass
     uint32_t mact;            // qubits the pass spans: tile qubits + enumerated ones
     uint32_t M;

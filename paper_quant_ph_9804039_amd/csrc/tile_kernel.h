@@ -50,6 +50,28 @@ __device__ __forceinline__ void st2(cplx<double> *p, cplx<double> a, cplx<double
     reinterpret_cast<double2 *>(p)[1] = make_double2(b.re, b.im);
 }
 
+// One amplitude at its natural alignment (8 bytes for complex64): the
+// struct itself only promises 4, and the compiler then splits the access in
+// two.
+__device__ __forceinline__ cplx<float> ld1(const cplx<float> *p)
+{
+    const float2 v = *static_cast<const float2 *>(__builtin_assume_aligned(p, 8));
+    return {v.x, v.y};
+}
+__device__ __forceinline__ void st1(cplx<float> *p, cplx<float> a)
+{
+    *static_cast<float2 *>(__builtin_assume_aligned(p, 8)) = make_float2(a.re, a.im);
+}
+__device__ __forceinline__ cplx<double> ld1(const cplx<double> *p)
+{
+    const double2 v = *static_cast<const double2 *>(__builtin_assume_aligned(p, 16));
+    return {v.x, v.y};
+}
+__device__ __forceinline__ void st1(cplx<double> *p, cplx<double> a)
+{
+    *static_cast<double2 *>(__builtin_assume_aligned(p, 16)) = make_double2(a.re, a.im);
+}
+
 // Register-pair loops of one operation on group bit P, specialised at
 // compile time.  Register r of a quantum holds the amplitude whose group bits
 // spell r, so the target bit is a compile-time property of r.  C: controls
@@ -480,6 +502,18 @@ k_tile(const TileArgs<R> A)
     for (int i = 0; i < G; ++i)
         o0[i] = spread(e0[i], srun, nsrun);
     const uint64_t rel0 = spread(j00, srun, nsrun);
+    // so is the last group's, in which the quantum goes back to HBM, and the
+    // renormalisation scale
+    uint32_t eL[G], jL;
+    bool pairL;
+    group_layout<R, G>(A, A.ngroups - 1, eL, jL, pairL);
+    uint64_t oL[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i)
+        oL[i] = spread(eL[i], srun, nsrun);
+    const uint64_t relL = spread(jL, srun, nsrun);
+    const bool scaled = A.scale_in != nullptr;
+    const R sc = scaled ? (R)*A.scale_in : R(1);
 
     cplx<R> x[1 << G];
     // each workgroup takes one contiguous block of tile numbers: neighbouring
@@ -489,15 +523,18 @@ k_tile(const TileArgs<R> A)
     const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
     const uint64_t t_end = (blockIdx.x + 1) * per < ntiles ? (blockIdx.x + 1) * per : ntiles;
     uint64_t tile_id = blockIdx.x * per;
+    // global index of tile element 0: the tile number spread over the
+    // enumerated qubits outside the tile (emask), in ascending order, plus
+    // the values of the untouched qubits.  Consecutive tile numbers step
+    // through the enumerated bits as a masked increment.
+    const uint64_t E = A.emask;
+    uint64_t ebits = spread(tile_id, crun, ncrun);
 
     for (; tile_id < t_end; ++tile_id) {
-        // global index of tile element 0: the tile number spread over the
-        // enumerated qubits outside the tile, in ascending order, plus the
-        // values of the untouched qubits
-        const uint64_t base = spread(tile_id, crun, ncrun) | A.base_or;
+        const uint64_t base = ebits | A.base_or;
+        ebits = ((ebits | ~E) + 1u) & E;
         load_quantum<R, G>(A.psi + (base | rel0), o0, pair00, x);
-        if (A.scale_in != nullptr) {
-            const R sc = (R)*A.scale_in;
+        if (scaled) {
 #pragma unroll
             for (int r = 0; r < (1 << G); ++r) {
                 x[r].re *= sc;
@@ -522,18 +559,23 @@ k_tile(const TileArgs<R> A)
                 } else {
 #pragma unroll
                     for (int r = 0; r < (1 << G); ++r)
-                        tile[elem_index<G>(j0, e, r)] = x[r];
+                        st1(tile + elem_index<G>(j0, e, r), x[r]);
                 }
                 __syncthreads();
                 group_layout<R, G>(A, gi, e, j0, pair0);
+                // fenced like the HBM loads, so each layout keeps its wide reads
                 if (pair0) {
+                    __asm__ volatile("" ::: "memory");
 #pragma unroll
                     for (int r = 0; r < (1 << G); r += 2)
                         ld2(tile + elem_index<G>(j0, e, r), x[r], x[r + 1]);
+                    __asm__ volatile("" ::: "memory");
                 } else {
+                    __asm__ volatile("" ::: "memory");
 #pragma unroll
                     for (int r = 0; r < (1 << G); ++r)
-                        x[r] = tile[elem_index<G>(j0, e, r)];
+                        x[r] = ld1(tile + elem_index<G>(j0, e, r));
+                    __asm__ volatile("" ::: "memory");
                 }
                 __syncthreads();
             }
@@ -541,11 +583,7 @@ k_tile(const TileArgs<R> A)
                               gi + 1 == A.ngroups);
         }
         // registers -> HBM in the last group's layout
-        uint64_t o[G];
-#pragma unroll
-        for (int i = 0; i < G; ++i)
-            o[i] = spread(e[i], srun, nsrun);
-        store_quantum<R, G>(A.psi + (base | spread(j0, srun, nsrun)), o, pair0, x);
+        store_quantum<R, G>(A.psi + (base | relL), oL, pairL, x);
         if (A.norm_out != nullptr) {
             double nsum = 0.0;
 #pragma unroll
