@@ -239,14 +239,15 @@ def bench_mc(q, cg, np):
 def bench_large(q, cg, np):
     """Large registers (64 GiB): M=33 complex64 and M=32 complex128, a
     500-gate circuit with half of the targets on the top 4 qubits, sigma =
-    1e-3.  Fused-pass HBM rate of each, with the automatic qubit remap (the
-    most used top qubits exchanged with low ones for the call) and without
-    it, and the complex64 register's error against the complex128 one at
-    M=33 (192 GiB on the device at once)."""
+    1e-3.  Fused-pass HBM rate of each: complex64 with the automatic qubit
+    remap (the most used top qubits exchanged with low ones for the call) and
+    without it, complex128 without it (its default) and with it forced; and
+    the complex64 register's error against the complex128 one at M=33
+    (192 GiB on the device at once)."""
     out = {"gates": 500, "top_bias": 0.5, "sigma": SIGMA}
     full = q.make_options(lazy_qubits=-1)
     runs = ((33, q.QSIM_C64, "m33_c64", 0), (33, q.QSIM_C64, "m33_c64_no_remap", -1),
-            (32, q.QSIM_C128, "m32_c128", 0), (32, q.QSIM_C128, "m32_c128_no_remap", -1))
+            (32, q.QSIM_C128, "m32_c128", 0), (32, q.QSIM_C128, "m32_c128_remap_forced", 1))
     for Ml, dt, name, remap in runs:
         gates = cg.random_circuit(Ml, 500, Ml, top_bias=0.5)
         try:

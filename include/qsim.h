@@ -126,7 +126,7 @@ typedef struct {
                             the dynamically allocated state vector, Sec. 3.2).
                             -1: every pass streams the whole register.  The
                             per-operation path (exec_mode 1) never skips. */
-    int remap_qubits;    /* 0 (default): on registers of 31 qubits or more, a
+    int remap_qubits;    /* 0 (default): on complex64 registers of 31 qubits or more, a
                             call whose operations use some of the top 6
                             qubits far more often than the low qubits just
                             above the always-tiled ones first exchanges up to

@@ -32,6 +32,15 @@ def test_large_register_with_top_heavy_targets_is_remapped():
     assert auto - base == 12 * pairs and 1 <= pairs <= 4
 
 
+def test_complex128_remaps_only_when_asked():
+    M = 32
+    gates = cg.random_circuit(M, 500, M, top_bias=0.5)
+    opt = q.make_options(lazy_qubits=-1)
+    _, auto = q.qsim_plan(M, q.QSIM_C128, gates, opt)
+    _, forced = q.qsim_plan(M, q.QSIM_C128, gates, q.make_options(lazy_qubits=-1, remap_qubits=1))
+    assert auto == len(gates) and forced > len(gates)
+
+
 def test_no_remap_below_the_size_or_without_top_heavy_use():
     gates = cg.random_circuit(30, 500, 30, top_bias=0.5)
     assert _nops(30, gates) == len(gates)
