@@ -197,6 +197,47 @@ __global__ void __launch_bounds__(kBlock3) k3_finish(const double *partial, uint
 // Marginal probabilities over up to six ions: block b bins elements
 // [b chunk, (b + 1) chunk) into LDS, thread by thread in a fixed order, and
 // writes its 3^m bins.
+// The same for at most three ions (27 bins): thread t takes elements lo + t,
+// lo + t + 256, ... of the block's chunk in that order into bins of its own
+// in LDS, and the block then adds each bin over the threads in thread order.
+constexpr uint32_t kFastMarginalBins = 27;
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock3) k3_marginal_few(const cplx<R> *psi, uint32_t n,
+                                                           uint32_t chunk, uint32_t m,
+                                                           const uint32_t *places,
+                                                           double *partial)
+{
+    __shared__ double tb[kFastMarginalBins * kBlock3];
+    uint32_t nb = 1, pl[3] = {1, 1, 1};
+    double inv[3] = {1.0, 1.0, 1.0};
+    for (uint32_t j = 0; j < m; ++j) {
+        nb *= 3;
+        pl[j] = places[j];
+        inv[j] = 1.0 / (double)pl[j];
+    }
+    for (uint32_t c = 0; c < nb; ++c)
+        tb[c * kBlock3 + threadIdx.x] = 0.0;
+    const uint32_t lo = blockIdx.x * chunk, hi = std::min(n, lo + chunk);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kBlock3) {
+        const double p = (double)psi[i].re * psi[i].re + (double)psi[i].im * psi[i].im;
+        uint32_t key = 0, kp = 1;
+        for (uint32_t j = 0; j < m; ++j) {
+            const uint32_t q = div_by(i, pl[j], inv[j]);
+            key += (q - 3u * (q / 3u)) * kp;
+            kp *= 3;
+        }
+        tb[key * kBlock3 + threadIdx.x] += p;
+    }
+    __syncthreads();
+    for (uint32_t c = threadIdx.x; c < nb; c += kBlock3) {
+        double s = 0.0;
+        for (uint32_t t = 0; t < kBlock3; ++t)
+            s += tb[c * kBlock3 + t];
+        partial[(uint64_t)nb * blockIdx.x + c] = s;
+    }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kBlock3) k3_marginal(const cplx<R> *psi, uint32_t n,
                                                        uint32_t chunk, uint32_t m,
@@ -740,14 +781,15 @@ int qsim3_probs(const qsim3_state *s, uint64_t ion_mask, double *out, size_t out
         while ((n + chunk - 1) / chunk > (uint32_t)kReduceBlocks3)
             chunk *= 2;
         const uint32_t g = (n + chunk - 1) / chunk;
+        const bool few = nb <= kFastMarginalBins;
         if (s->dtype == QSIM_C64)
-            hipLaunchKernelGGL((k3_marginal<float>), dim3(g), dim3(kBlock3), 0, s->stream,
-                               (const cplx<float> *)s->psi, n, chunk, (uint32_t)m, ms->d_places,
-                               ms->d_partial);
+            hipLaunchKernelGGL(few ? k3_marginal_few<float> : k3_marginal<float>, dim3(g),
+                               dim3(kBlock3), 0, s->stream, (const cplx<float> *)s->psi, n, chunk,
+                               (uint32_t)m, ms->d_places, ms->d_partial);
         else
-            hipLaunchKernelGGL((k3_marginal<double>), dim3(g), dim3(kBlock3), 0, s->stream,
-                               (const cplx<double> *)s->psi, n, chunk, (uint32_t)m, ms->d_places,
-                               ms->d_partial);
+            hipLaunchKernelGGL(few ? k3_marginal_few<double> : k3_marginal<double>, dim3(g),
+                               dim3(kBlock3), 0, s->stream, (const cplx<double> *)s->psi, n,
+                               chunk, (uint32_t)m, ms->d_places, ms->d_partial);
         hipLaunchKernelGGL(k3_finish, dim3(1), dim3(kBlock3), 0, s->stream, ms->d_partial, g,
                            (uint32_t)nb, ms->d_out);
         HIP3(hipGetLastError(), "marginal");
