@@ -287,9 +287,11 @@ def bench_three_state(q, cg, np):
     """The detailed three-state model (Sec. 2.0, Sec. 3.0): 19 ions, 3^19 =
     1.16e9 complex64 amplitudes (9.3 GB), 100 random gates lowered to laser
     transformations (a CNOT is five, through the auxiliary level) with angle
-    errors and flips.  One kernel per transformation; each rewrites the two
-    levels it couples, 2/3 of the register (1/9 when it is conditional on
-    another ion's level)."""
+    errors and flips.  Fused passes (runs of transformations applied tile by
+    tile in LDS, one HBM read and write per run) beside one launch per
+    transformation (each rewrites the two levels it couples, 2/3 of the
+    register, 2/9 when conditional), and how far apart the two are on the
+    first 65536 amplitudes (rounding: FMA contraction may differ)."""
     M3, G3 = 19, 100
     gates = cg.random_circuit(M3, G3, 319, kinds=(cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT))
     pulses = q.qsim3_lower(gates, M3)
@@ -298,25 +300,34 @@ def bench_three_state(q, cg, np):
     amps = sum(pair_amps // (3 if p["cond_ion"] >= 0 else 1) for p in pulses)
     out = {"num_ions": M3, "amplitudes": 3 ** M3, "gates": G3, "transformations": len(pulses),
            "dtype": "c64"}
-    with q.State3(M3, q.QSIM_C64) as s:
-        s.apply(gates[:4])
-        s.synchronize()
-        walls = []
-        for r in range(2):
-            s.reset(0)
-            s.inject_errors(SIGMA, P_FLIP, P_FLIP, seed=319, trial=r)
+    results = {}
+    for name, mode in (("fused", 0), ("per_transformation", 1)):
+        with q.State3(M3, q.QSIM_C64, q.make_options(exec_mode=mode)) as s:
+            s.apply(gates[:4])
             s.synchronize()
-            t0 = time.perf_counter()
-            s.apply(gates)
-            s.synchronize()
-            walls.append(time.perf_counter() - t0)
-        wall = min(walls)
-        norm = float(np.sum(s.probs(1)))
-    gbps = 2 * amps * eb / wall / 1e9
-    out.update({"seconds": wall, "transformations_per_s": len(pulses) / wall,
-                "amplitude_updates_per_s": amps / wall,
-                "algorithmic_GBps": gbps, "hbm_frac": gbps / HBM_PEAK_GBS,
-                "norm_after": norm})
+            walls = []
+            for r in range(2):
+                s.reset(0)
+                s.inject_errors(SIGMA, P_FLIP, P_FLIP, seed=319, trial=r)
+                s.synchronize()
+                t0 = time.perf_counter()
+                s.apply(gates)
+                s.synchronize()
+                walls.append(time.perf_counter() - t0)
+            wall = min(walls)
+            norm = float(np.sum(s.probs(1)))
+            results[name] = s.amplitudes(0, 1 << 16)
+        rec = {"seconds": wall, "transformations_per_s": len(pulses) / wall,
+               "amplitude_updates_per_s": amps / wall, "norm_after": norm}
+        if mode == 1:
+            # one launch per transformation: its algorithmic bytes are the
+            # coupled levels, read and written
+            gbps = 2 * amps * eb / wall / 1e9
+            rec.update({"algorithmic_GBps": gbps, "hbm_frac": gbps / HBM_PEAK_GBS})
+        out[name] = rec
+    out["fused_vs_per_transformation_max_abs_diff"] = float(
+        np.max(np.abs(results["fused"] - results["per_transformation"])))
+    out["speedup_fused"] = out["per_transformation"]["seconds"] / out["fused"]["seconds"]
     return out
 
 

@@ -430,7 +430,10 @@ typedef struct {
 } qsim3_pulse;
 
 /* Register of num_ions (1..20) ions in dtype, set to |0...0>; the options
- * used are device and hip_stream.  EINVAL / ENOMEM as qsim_create. */
+ * used are device, hip_stream and exec_mode (1: one launch per
+ * transformation; otherwise runs of transformations whose ions fit one LDS
+ * tile are applied as fused passes, on registers larger than a tile).
+ * EINVAL / ENOMEM as qsim_create. */
 int qsim3_create(int num_ions, int dtype, const qsim_options *opt, qsim3_state **out);
 int qsim3_destroy(qsim3_state *s);
 /* Basis state |basis_index> (0 <= basis_index < 3^M), step counter 0. */

@@ -6,9 +6,10 @@
 // (Sec. 3.1).  State index i = sum_q d_q 3^q, d_q the level of ion q.
 //
 // The host lowers each gate to transformations (five for a CNOT), draws
-// their angle errors and the step's flips, and launches one kernel per
-// transformation; a launch reads and writes the two levels a, b of one ion,
-// i.e. 2/3 of the register.
+// their angle errors and the step's flips, and applies them in order: runs
+// whose ions fit one LDS tile as fused passes (k3_tile, one HBM read and
+// write per run), else one launch per transformation (k3_pairs, reading and
+// writing the two levels a, b of one ion, i.e. 2/3 of the register).
 //
 // Readings of the paper (its pulse sequences are not given):
 //   - transformation on ion q between levels a < b, angle theta, phase phi:
@@ -126,6 +127,175 @@ __global__ void __launch_bounds__(kBlock3) k3_init(cplx<R> *psi, uint32_t n, uin
     const uint32_t stride = gridDim.x * kBlock3;
     for (uint32_t i = blockIdx.x * kBlock3 + threadIdx.x; i < n; i += stride)
         psi[i] = {R(i == k ? 1 : 0), R(0)};
+}
+
+// ------------------------------------------------------------ fused passes
+//
+// A transformation only mixes amplitudes that differ in its ion's level, so
+// for a set T of k ions the 3^k amplitudes that share the levels of every
+// ion outside T (a tile) are closed under every transformation on an ion of
+// T, and a condition on an ion outside T is a constant of the tile.  A run
+// of transformations whose ions lie in T is applied tile by tile: a
+// workgroup loads the tile into LDS, applies the run in order (a barrier
+// between transformations), and writes the tile back: one HBM read and
+// write for the whole run instead of one per transformation.  T always holds
+// the lowest ions, so a tile is runs of 3^low contiguous amplitudes.
+
+constexpr uint32_t kLowIons3 = 3;
+template <typename R>
+constexpr int kTileIons3 = sizeof(R) == 4 ? 8 : 7;   // 3^8 x 8 B = 51 KiB, 3^7 x 16 B = 34 KiB
+template <typename R>
+constexpr int kMaxRun3 = sizeof(R) == 4 ? 48 : 36;   // transformations per pass (4 KiB of arguments)
+
+__host__ __device__ constexpr uint32_t pow3c(int e) { return e <= 0 ? 1u : 3u * pow3c(e - 1); }
+
+template <typename R>
+struct Run3Op {
+    cplx<R> u[4];        // u00 u01 u10 u11 (kPairMat)
+    uint32_t pos;        // tile position of the ion
+    uint32_t place;      // 3^pos (inside the tile)
+    uint32_t a, b;       // levels, a < b
+    uint32_t mode;       // PairMode
+    uint32_t cplace;     // condition ion inside the tile: 3^its position, else 0
+    uint32_t oplace;     // condition ion outside the tile: 3^ion, else 0
+    uint32_t clevel;
+    float inv_cplace;    // 1 / cplace
+};
+
+template <typename R>
+struct Tile3Args {
+    cplx<R> *psi;
+    uint32_t ntiles;            // 3^(M - k)
+    uint32_t nout;              // ions outside the tile
+    uint32_t nops;
+    uint32_t tplace[kMaxIons];  // 3^ion of tile positions 0..k-1 (positions < low: ion = position)
+    uint32_t oplace[kMaxIons];  // 3^ion of the ions outside the tile, ascending
+    Run3Op<R> ops[kMaxRun3<R>];
+};
+
+constexpr int kTileBlock3 = 512;
+
+// One transformation on the tile in LDS: pair w of the N / 3 pairs of levels
+// a, b of the ion at tile place P.  Each thread takes its pairs w = tid,
+// tid + 512, ... all at once (the pairs are disjoint), so their LDS reads are
+// in flight together.
+template <typename R, uint32_t P, uint32_t N>
+__device__ __forceinline__ void tile_pairs(cplx<R> *t, const Run3Op<R> &op)
+{
+    constexpr uint32_t W = (N / 3u + kTileBlock3 - 1) / kTileBlock3;
+    uint32_t ia[W];
+    bool on[W];
+    cplx<R> x[W], y[W];
+    const uint32_t d = (op.b - op.a) * P;
+#pragma unroll
+    for (uint32_t m = 0; m < W; ++m) {
+        const uint32_t w = m * kTileBlock3 + threadIdx.x;
+        const uint32_t hi = w / P, lo = w - hi * P;
+        const uint32_t i = hi * 3u * P + op.a * P + lo;
+        bool ok = w < N / 3u;
+        if (ok && op.cplace != 0) {
+            // i < 3^8: the FP32 quotient is off by at most one, which the
+            // remainder corrects
+            uint32_t q = (uint32_t)((float)i * op.inv_cplace);
+            const int r = (int)i - (int)(q * op.cplace);
+            q = r < 0 ? q - 1u : (r >= (int)op.cplace ? q + 1u : q);
+            ok = q - 3u * (q / 3u) == op.clevel;
+        }
+        ia[m] = i;
+        on[m] = ok;
+        if (ok) {
+            x[m] = t[i];
+            y[m] = t[i + d];
+        }
+    }
+#pragma unroll
+    for (uint32_t m = 0; m < W; ++m) {
+        if (!on[m])
+            continue;
+        const uint32_t i = ia[m];
+        if (op.mode == kPairSwap) {
+            t[i] = y[m];
+            t[i + d] = x[m];
+        } else if (op.mode == kPairNegB) {
+            t[i + d] = {-y[m].re, -y[m].im};
+        } else {
+            t[i] = qsim::cmad2(op.u[0], x[m], op.u[1], y[m]);
+            t[i + d] = qsim::cmad2(op.u[2], x[m], op.u[3], y[m]);
+        }
+    }
+}
+
+static_assert(sizeof(Tile3Args<float>) <= 4096 && sizeof(Tile3Args<double>) <= 4096,
+              "kernel arguments must fit 4 KiB");
+
+template <typename R>
+__global__ void __launch_bounds__(kTileBlock3) k3_tile(const Tile3Args<R> A)
+{
+    constexpr int K = kTileIons3<R>;
+    constexpr uint32_t N = pow3c(K), L = pow3c(kLowIons3), H = pow3c(K - kLowIons3);
+    __shared__ cplx<R> t[N];
+    __shared__ uint32_t offhi[H];
+    // offset of tile element e from the tile's base: e % L covers the low
+    // ions (contiguous), offhi[e / L] the others
+    for (uint32_t h = threadIdx.x; h < H; h += kTileBlock3) {
+        uint32_t off = 0, v = h;
+        for (int j = kLowIons3; j < K; ++j) {
+            const uint32_t q = v / 3u;
+            off += (v - 3u * q) * A.tplace[j];
+            v = q;
+        }
+        offhi[h] = off;
+    }
+    __syncthreads();
+    const uint32_t per = (A.ntiles + gridDim.x - 1) / gridDim.x;
+    const uint32_t t0 = blockIdx.x * per;
+    const uint32_t t1 = t0 + per < A.ntiles ? t0 + per : A.ntiles;
+    for (uint32_t tile = t0; tile < t1; ++tile) {
+        uint32_t base = 0, v = tile;
+        for (uint32_t m = 0; m < A.nout; ++m) {
+            const uint32_t q = v / 3u;
+            base += (v - 3u * q) * A.oplace[m];
+            v = q;
+        }
+        // batches of loads in flight at once, then into LDS
+        constexpr uint32_t U = 8;
+        for (uint32_t e0 = 0; e0 < N; e0 += U * kTileBlock3) {
+            cplx<R> v[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t e = e0 + u * kTileBlock3 + threadIdx.x;
+                if (e < N)
+                    v[u] = A.psi[base + e % L + offhi[e / L]];
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t e = e0 + u * kTileBlock3 + threadIdx.x;
+                if (e < N)
+                    t[e] = v[u];
+            }
+        }
+        __syncthreads();
+        for (uint32_t o = 0; o < A.nops; ++o) {
+            const Run3Op<R> &op = A.ops[o];
+            if (op.oplace != 0 && (base / op.oplace) % 3u != op.clevel)
+                continue;  // uniform over the workgroup: the condition is off for this tile
+            switch (op.pos) {  // the ion's place in the tile as a constant divisor
+            case 0: tile_pairs<R, pow3c(0), N>(t, op); break;
+            case 1: tile_pairs<R, pow3c(1), N>(t, op); break;
+            case 2: tile_pairs<R, pow3c(2), N>(t, op); break;
+            case 3: tile_pairs<R, pow3c(3), N>(t, op); break;
+            case 4: tile_pairs<R, pow3c(4), N>(t, op); break;
+            case 5: tile_pairs<R, pow3c(5), N>(t, op); break;
+            case 6: tile_pairs<R, pow3c(6), N>(t, op); break;
+            default: if constexpr (K > 7) tile_pairs<R, pow3c(7), N>(t, op); break;
+            }
+            __syncthreads();
+        }
+#pragma unroll 8
+        for (uint32_t e = threadIdx.x; e < N; e += kTileBlock3)
+            A.psi[base + e % L + offhi[e / L]] = t[e];
+        __syncthreads();
+    }
 }
 
 __device__ __forceinline__ double wave_sum3(double v)
@@ -400,6 +570,7 @@ struct qsim3_state {
     double *d_stage = nullptr;
     size_t stage_bytes = 0;
     uint64_t pulses = 0;
+    bool per_pulse = false;  // exec_mode 1: one launch per transformation
 };
 
 namespace {
@@ -450,12 +621,115 @@ hipError_t pairs(qsim3_state *s, int ion, int a, int b, int cion, int clev, uint
                                 : launch_pairs<double>(s, ion, a, b, cion, clev, mode, u);
 }
 
-int apply_pulse(qsim3_state *s, const qsim3_pulse &p, double eps)
-{
+// One transformation (or exact flip) with its FP64 matrix, ready to launch.
+struct Xform {
+    int ion, a, b, cion, clevel;
+    uint32_t mode;
     double u[8];
-    pulse_matrix(p, eps, u);
-    HIP3(pairs(s, p.ion, p.a, p.b, p.cond_ion, p.cond_level, kPairMat, u), "transformation");
-    ++s->pulses;
+};
+
+Xform make_pulse(const qsim3_pulse &p, double eps)
+{
+    Xform x{p.ion, p.a, p.b, p.cond_ion, p.cond_level, kPairMat, {}};
+    pulse_matrix(p, eps, x.u);
+    return x;
+}
+
+Xform make_flip(int ion, uint32_t mode)
+{
+    return Xform{ion, 0, 1, -1, 0, mode, {1, 0, 0, 0, 0, 0, 1, 0}};
+}
+
+// A run of transformations as one fused pass: tile ions T (the low ions,
+// then the run's ions in ascending order), the rest enumerate the tiles.
+template <typename R>
+hipError_t launch_run(qsim3_state *s, const Xform *x, size_t n, const std::vector<int> &T)
+{
+    Tile3Args<R> A{};
+    A.psi = static_cast<cplx<R> *>(s->psi);
+    const int M = s->M, K = kTileIons3<R>;
+    int pos_of[kMaxIons];
+    for (int q = 0; q < M; ++q)
+        pos_of[q] = -1;
+    for (int j = 0; j < K; ++j) {
+        A.tplace[j] = (uint32_t)pow3(T[j]);
+        pos_of[T[j]] = j;
+    }
+    A.nout = 0;
+    for (int q = 0; q < M; ++q)
+        if (pos_of[q] < 0)
+            A.oplace[A.nout++] = (uint32_t)pow3(q);
+    A.ntiles = (uint32_t)pow3(M - K);
+    A.nops = (uint32_t)n;
+    for (size_t i = 0; i < n; ++i) {
+        Run3Op<R> &op = A.ops[i];
+        op.pos = (uint32_t)pos_of[x[i].ion];
+        op.place = pow3c((int)op.pos);
+        op.a = (uint32_t)x[i].a;
+        op.b = (uint32_t)x[i].b;
+        op.mode = x[i].mode;
+        op.cplace = 0;
+        op.oplace = 0;
+        op.clevel = (uint32_t)x[i].clevel;
+        op.inv_cplace = 0.0f;
+        if (x[i].cion >= 0) {
+            if (pos_of[x[i].cion] >= 0) {
+                op.cplace = pow3c(pos_of[x[i].cion]);
+                op.inv_cplace = 1.0f / (float)op.cplace;
+            } else {
+                op.oplace = (uint32_t)pow3(x[i].cion);
+            }
+        }
+        for (int k = 0; k < 4; ++k)
+            op.u[k] = {(R)x[i].u[2 * k], (R)x[i].u[2 * k + 1]};
+    }
+    const uint32_t grid = std::min<uint32_t>(A.ntiles, 256u * 8u);
+    hipLaunchKernelGGL((k3_tile<R>), dim3(grid), dim3(kTileBlock3), 0, s->stream, A);
+    return hipGetLastError();
+}
+
+// Apply transformations in order: fused passes over runs whose ions fit one
+// tile (registers larger than a tile, exec_mode other than 1), else one
+// launch each.
+int apply_xforms(qsim3_state *s, const std::vector<Xform> &xs)
+{
+    const int K = s->dtype == QSIM_C64 ? kTileIons3<float> : kTileIons3<double>;
+    const size_t cap = s->dtype == QSIM_C64 ? (size_t)kMaxRun3<float> : (size_t)kMaxRun3<double>;
+    if (s->per_pulse || s->M <= K) {
+        for (const Xform &x : xs)
+            HIP3(pairs(s, x.ion, x.a, x.b, x.cion, x.clevel, x.mode, x.u), "transformation");
+        return QSIM_OK;
+    }
+    size_t i = 0;
+    while (i < xs.size()) {
+        uint32_t in = (1u << kLowIons3) - 1;  // ions of T
+        int nin = (int)kLowIons3;
+        size_t j = i;
+        for (; j < xs.size() && j - i < cap; ++j) {
+            const uint32_t bit = 1u << xs[j].ion;
+            if (!(in & bit)) {
+                if (nin == K)
+                    break;
+                in |= bit;
+                ++nin;
+            }
+        }
+        // fill T to K ions with the lowest ions not yet in it
+        for (int q = 0; q < s->M && nin < K; ++q)
+            if (!(in & (1u << q))) {
+                in |= 1u << q;
+                ++nin;
+            }
+        std::vector<int> T;
+        for (int q = 0; q < s->M; ++q)
+            if (in & (1u << q))
+                T.push_back(q);
+        if (s->dtype == QSIM_C64)
+            HIP3(launch_run<float>(s, &xs[i], j - i, T), "fused pass");
+        else
+            HIP3(launch_run<double>(s, &xs[i], j - i, T), "fused pass");
+        i = j;
+    }
     return QSIM_OK;
 }
 
@@ -538,6 +812,7 @@ int qsim3_create(int num_ions, int dtype, const qsim_options *opt, qsim3_state *
         s->dtype = dtype;
         s->device = o.device;
         s->n = pow3(num_ions);
+        s->per_pulse = o.exec_mode == 1;
         e = hipSetDevice(o.device);
         if (e == hipSuccess) {
             if (o.hip_stream) {
@@ -655,27 +930,30 @@ int qsim3_apply_circuit(qsim3_state *s, const qsim_gate *gates, size_t n)
         const bool flips = s->armed && (s->em.p_bitflip > 0.0 || s->em.p_phaseflip > 0.0);
         const uint64_t tb = flips ? qsim::flip_threshold(s->em.p_bitflip) : 0;
         const uint64_t tp = flips ? qsim::flip_threshold(s->em.p_phaseflip) : 0;
-        const double ident[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+        std::vector<Xform> xs;
+        uint64_t npulses = 0;
         for (size_t k = 0; k < n; ++k) {
             const uint64_t step = s->step + k;
             Lowering L;
             L.gate(gates[k]);
-            for (size_t j = 0; j < L.out.size(); ++j) {
-                rc = apply_pulse(s, L.out[j], ang ? pulse_eps(s->em, step, j) : 0.0);
-                if (rc != QSIM_OK)
-                    return rc;
-            }
+            for (size_t j = 0; j < L.out.size(); ++j)
+                xs.push_back(make_pulse(L.out[j], ang ? pulse_eps(s->em, step, j) : 0.0));
+            npulses += L.out.size();
             if (!flips)
                 continue;
             for (int q = 0; q < s->M; ++q) {
                 const qsim::u64x4 r = qsim::philox4x64_10(step, (uint64_t)q, qsim::kStreamFlip, 0,
                                                           s->em.seed, s->em.trial);
                 if ((r.w[0] >> 32) < tb)
-                    HIP3(pairs(s, q, 0, 1, -1, 0, kPairSwap, ident), "bit flip");
+                    xs.push_back(make_flip(q, kPairSwap));
                 if ((r.w[1] >> 32) < tp)
-                    HIP3(pairs(s, q, 0, 1, -1, 0, kPairNegB, ident), "phase flip");
+                    xs.push_back(make_flip(q, kPairNegB));
             }
         }
+        rc = apply_xforms(s, xs);
+        if (rc != QSIM_OK)
+            return rc;
+        s->pulses += npulses;
         s->step += n;
         return QSIM_OK;
     });
@@ -690,11 +968,13 @@ int qsim3_apply_pulses(qsim3_state *s, const qsim3_pulse *p, size_t n)
             if (!pulse_valid(p[k], s->M))
                 return qsim::set_error(QSIM_EINVAL, "transformation %zu is malformed", k);
         HIP3(hipSetDevice(s->device), "hipSetDevice");
-        for (size_t k = 0; k < n; ++k) {
-            const int rc = apply_pulse(s, p[k], 0.0);
-            if (rc != QSIM_OK)
-                return rc;
-        }
+        std::vector<Xform> xs;
+        for (size_t k = 0; k < n; ++k)
+            xs.push_back(make_pulse(p[k], 0.0));
+        const int rc = apply_xforms(s, xs);
+        if (rc != QSIM_OK)
+            return rc;
+        s->pulses += n;
         return QSIM_OK;
     });
 }

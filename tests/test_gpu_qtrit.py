@@ -164,3 +164,56 @@ def test_largest_register_cnot_and_x_on_basis_states():
         # each X is a pi pulse, -i X: the two of ion 10 leave a global phase
         assert abs(abs(a[2]) - 1.0) < 1e-6 and np.max(np.abs(np.delete(a, 2))) < 1e-15
         assert abs(float(np.sum(s.probs(1 << 19))) - 1.0) < 1e-6
+
+
+@pytest.mark.parametrize("dtype", [q.QSIM_C128, q.QSIM_C64])
+@pytest.mark.parametrize("M,seed", [(9, 31), (12, 32)])
+def test_fused_passes_vs_oracle_and_per_transformation_path(dtype, M, seed):
+    """Registers larger than one tile (3^8 complex64 / 3^7 complex128
+    amplitudes) run fused passes: against the oracle with errors and flips,
+    and against one launch per transformation (exec_mode 1), which does the
+    same operations on each pair (the compiler may contract them into FMAs
+    differently, so the two agree to rounding, not bit for bit)."""
+    print(f"three-state fused M={M} dtype={dtype}", flush=True)
+    g = cg.random_circuit(M, 90, 500 + seed, kinds=KINDS)
+    em = oracle.Errors(sigma=0.03, p_bitflip=0.01, p_phaseflip=0.01, seed=seed, trial=2)
+    ref = oracle.as_complex(oracle.simulate3(M, g, em))
+    out = []
+    for mode in (0, 1):
+        with q.State3(M, dtype, q.make_options(exec_mode=mode)) as s:
+            s.inject_errors(em.sigma, em.p_bitflip, em.p_phaseflip, em.seed, em.trial)
+            s.apply(g[:40])
+            s.apply(g[40:])
+            out.append(s.amplitudes())
+    assert np.max(np.abs(out[0] - ref)) <= TOL[dtype]
+    assert np.max(np.abs(out[1] - ref)) <= TOL[dtype]
+    assert np.max(np.abs(out[0] - out[1])) <= TOL[dtype]
+
+
+def test_fused_conditional_transformations_inside_and_outside_the_tile():
+    """Conditions on ions inside and outside a pass's tile (M = 11 complex128:
+    a tile holds 7 of the 11 ions)."""
+    M = 11
+    rng = np.random.default_rng(77)
+    pulses = []
+    for _ in range(120):
+        a, b = sorted(rng.choice(3, 2, replace=False).tolist())
+        ion = int(rng.integers(M))
+        p = {"kind": int(rng.integers(2)), "ion": ion, "a": a, "b": b, "cond_ion": -1,
+             "cond_level": 0, "theta": float(rng.uniform(0, 7)), "phi": float(rng.uniform(-3, 3))}
+        if rng.random() < 0.7:
+            p["cond_ion"] = int(rng.choice([x for x in range(M) if x != ion]))
+            p["cond_level"] = int(rng.integers(3))
+        pulses.append(p)
+    psi = oracle.init3(M, 5)
+    # start from a spread state: every ion through a rotation first
+    spread = [{"kind": 0, "ion": q_, "a": 0, "b": 1, "cond_ion": -1, "cond_level": 0,
+               "theta": 1.1 + 0.1 * q_, "phi": 0.3} for q_ in range(M)]
+    spread += [{"kind": 0, "ion": q_, "a": 1, "b": 2, "cond_ion": -1, "cond_level": 0,
+                "theta": 0.7, "phi": -0.2 * q_} for q_ in range(M)]
+    for p in spread + pulses:
+        oracle.apply_pulse3(psi, M, p)
+    with q.State3(M, q.QSIM_C128) as s:
+        s.reset(5)
+        s.apply_pulses(spread + pulses)
+        assert np.max(np.abs(s.amplitudes() - oracle.as_complex(psi))) < 1e-12
