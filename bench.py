@@ -310,20 +310,25 @@ def bench_three_state(q, cg, np):
                 s.reset(0)
                 s.inject_errors(SIGMA, P_FLIP, P_FLIP, seed=319, trial=r)
                 s.synchronize()
+                l0 = s.info()["launches"]
                 t0 = time.perf_counter()
                 s.apply(gates)
                 s.synchronize()
                 walls.append(time.perf_counter() - t0)
+                launches = s.info()["launches"] - l0
             wall = min(walls)
             norm = float(np.sum(s.probs(1)))
             results[name] = s.amplitudes(0, 1 << 16)
         rec = {"seconds": wall, "transformations_per_s": len(pulses) / wall,
-               "amplitude_updates_per_s": amps / wall, "norm_after": norm}
+               "amplitude_updates_per_s": amps / wall, "norm_after": norm, "launches": launches}
         if mode == 1:
             # one launch per transformation: its algorithmic bytes are the
             # coupled levels, read and written
             gbps = 2 * amps * eb / wall / 1e9
-            rec.update({"algorithmic_GBps": gbps, "hbm_frac": gbps / HBM_PEAK_GBS})
+        else:
+            # a fused pass reads and writes the whole register once
+            gbps = launches * 2 * 3 ** M3 * eb / wall / 1e9
+        rec.update({"algorithmic_GBps": gbps, "hbm_frac": gbps / HBM_PEAK_GBS})
         out[name] = rec
     out["fused_vs_per_transformation_max_abs_diff"] = float(
         np.max(np.abs(results["fused"] - results["per_transformation"])))
@@ -424,7 +429,8 @@ def cpu_leg(q, np, gates, mc_gates, mc_F, budget_s: float = 15.0, t1_budget_s: f
     all host cores (timed around the gate loop) and on one core; the GPU
     complex64 and complex128 registers against the oracle's state after the
     same gates; the oracle's Monte Carlo trials on the first 64 trials of the
-    batched workload, against the GPU's fidelities."""
+    batched workload, against the GPU's fidelities; the three-state oracle on
+    16 ions."""
     import oracle
     oracle.build(force=False)
     em = oracle.Errors(sigma=SIGMA, p_bitflip=P_FLIP, p_phaseflip=P_FLIP, seed=ERROR_SEED, trial=0)
@@ -451,6 +457,18 @@ def cpu_leg(q, np, gates, mc_gates, mc_F, budget_s: float = 15.0, t1_budget_s: f
                       f"{dt:.1f} s on {cores} host threads",
             "t1": {"value": done1 * float(1 << M) / dt1, "cores": 1, "gates": done1,
                    "seconds": dt1}}
+    # the three-state oracle on the largest register it takes (16 ions), the
+    # first 10 gates of the three-state workload's kinds
+    import circuitgen as cg
+    Mo = 16
+    go = cg.random_circuit(Mo, 10, 316, kinds=(cg.H, cg.RZ, cg.X, cg.Z, cg.CNOT))
+    po = q.qsim3_lower(go, Mo)
+    t3 = time.perf_counter()
+    oracle.simulate3(Mo, go)
+    dt3 = time.perf_counter() - t3
+    ao = sum(2 * 3 ** (Mo - 1) // (3 if p["cond_ion"] >= 0 else 1) for p in po)
+    base["three_state"] = {"num_ions": Mo, "transformations": len(po), "seconds": dt3,
+                           "amplitude_updates_per_s": ao / dt3, "cores": cores}
     # GPU registers after the same gates, against the oracle's state
     ref = psi.view(np.complex128)
     nref = float(np.vdot(ref, ref).real)

@@ -461,9 +461,11 @@ int qsim3_probs(const qsim3_state *s, uint64_t ion_mask, double *out, size_t out
 /* Amplitudes [offset, offset + count) as interleaved FP64 re/im pairs. */
 int qsim3_get_amplitudes(const qsim3_state *s, uint64_t offset, uint64_t count, double *out);
 int qsim3_synchronize(qsim3_state *s);
-/* Register size, dtype, step counter and transformations applied. */
+/* Register size, dtype, step counter, transformations applied and state
+ * kernel launches (fused passes or one per transformation) since create;
+ * any pointer may be NULL. */
 int qsim3_info(const qsim3_state *s, int *num_ions, int *dtype, uint64_t *step,
-               uint64_t *transformations);
+               uint64_t *transformations, uint64_t *launches);
 
 /* Wait for all work queued on the state's stream. */
 int qsim_synchronize(qsim_state *s);

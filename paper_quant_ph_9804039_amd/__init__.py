@@ -167,7 +167,7 @@ def lib() -> ctypes.CDLL:
         "qsim3_get_amplitudes": [vp, u64, u64, dp],
         "qsim3_synchronize": [vp],
         "qsim3_info": [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                       ctypes.POINTER(u64), ctypes.POINTER(u64)],
+                       ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -594,8 +594,9 @@ class State3:
         return self
 
     def info(self) -> dict:
-        M, dt, step, nt = ctypes.c_int(), ctypes.c_int(), ctypes.c_uint64(), ctypes.c_uint64()
+        M, dt, step = ctypes.c_int(), ctypes.c_int(), ctypes.c_uint64()
+        nt, nl = ctypes.c_uint64(), ctypes.c_uint64()
         _check(lib().qsim3_info(self.h, ctypes.byref(M), ctypes.byref(dt), ctypes.byref(step),
-                                ctypes.byref(nt)))
+                                ctypes.byref(nt), ctypes.byref(nl)))
         return {"num_ions": M.value, "dtype": dt.value, "step": step.value,
-                "transformations": nt.value}
+                "transformations": nt.value, "launches": nl.value}

@@ -570,6 +570,7 @@ struct qsim3_state {
     double *d_stage = nullptr;
     size_t stage_bytes = 0;
     uint64_t pulses = 0;
+    uint64_t launches = 0;   // state kernel launches (fused passes or per transformation)
     bool per_pulse = false;  // exec_mode 1: one launch per transformation
 };
 
@@ -696,8 +697,10 @@ int apply_xforms(qsim3_state *s, const std::vector<Xform> &xs)
     const int K = s->dtype == QSIM_C64 ? kTileIons3<float> : kTileIons3<double>;
     const size_t cap = s->dtype == QSIM_C64 ? (size_t)kMaxRun3<float> : (size_t)kMaxRun3<double>;
     if (s->per_pulse || s->M <= K) {
-        for (const Xform &x : xs)
+        for (const Xform &x : xs) {
             HIP3(pairs(s, x.ion, x.a, x.b, x.cion, x.clevel, x.mode, x.u), "transformation");
+            ++s->launches;
+        }
         return QSIM_OK;
     }
     size_t i = 0;
@@ -728,6 +731,7 @@ int apply_xforms(qsim3_state *s, const std::vector<Xform> &xs)
             HIP3(launch_run<float>(s, &xs[i], j - i, T), "fused pass");
         else
             HIP3(launch_run<double>(s, &xs[i], j - i, T), "fused pass");
+        ++s->launches;
         i = j;
     }
     return QSIM_OK;
@@ -1124,7 +1128,7 @@ int qsim3_synchronize(qsim3_state *s)
 }
 
 int qsim3_info(const qsim3_state *s, int *num_ions, int *dtype, uint64_t *step,
-               uint64_t *transformations)
+               uint64_t *transformations, uint64_t *launches)
 {
     return qsim::guarded(__func__, [&]() -> int {
         if (s == nullptr)
@@ -1133,6 +1137,7 @@ int qsim3_info(const qsim3_state *s, int *num_ions, int *dtype, uint64_t *step,
         if (dtype) *dtype = s->dtype;
         if (step) *step = s->step;
         if (transformations) *transformations = s->pulses;
+        if (launches) *launches = s->launches;
         return QSIM_OK;
     });
 }

@@ -179,12 +179,17 @@ def test_fused_passes_vs_oracle_and_per_transformation_path(dtype, M, seed):
     em = oracle.Errors(sigma=0.03, p_bitflip=0.01, p_phaseflip=0.01, seed=seed, trial=2)
     ref = oracle.as_complex(oracle.simulate3(M, g, em))
     out = []
+    npulses = len(q.qsim3_lower(g, M))
     for mode in (0, 1):
         with q.State3(M, dtype, q.make_options(exec_mode=mode)) as s:
             s.inject_errors(em.sigma, em.p_bitflip, em.p_phaseflip, em.seed, em.trial)
             s.apply(g[:40])
             s.apply(g[40:])
             out.append(s.amplitudes())
+            info = s.info()
+            assert info["transformations"] == npulses
+            # fused: a few runs; per transformation: one launch each (flips too)
+            assert (info["launches"] < npulses // 3) if mode == 0 else (info["launches"] >= npulses)
     assert np.max(np.abs(out[0] - ref)) <= TOL[dtype]
     assert np.max(np.abs(out[1] - ref)) <= TOL[dtype]
     assert np.max(np.abs(out[0] - out[1])) <= TOL[dtype]
