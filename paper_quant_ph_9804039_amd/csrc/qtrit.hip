@@ -160,6 +160,7 @@ struct Run3Op {
     uint32_t oplace;     // condition ion outside the tile: 3^ion, else 0
     uint32_t clevel;
     float inv_cplace;    // 1 / cplace
+    float inv_place;     // 1 / place
 };
 
 template <typename R>
@@ -179,18 +180,23 @@ constexpr int kTileBlock3 = 512;
 // a, b of the ion at tile place P.  Each thread takes its pairs w = tid,
 // tid + 512, ... all at once (the pairs are disjoint), so their LDS reads are
 // in flight together.
-template <typename R, uint32_t P, uint32_t N>
+template <typename R, uint32_t N>
 __device__ __forceinline__ void tile_pairs(cplx<R> *t, const Run3Op<R> &op)
 {
     constexpr uint32_t W = (N / 3u + kTileBlock3 - 1) / kTileBlock3;
     uint32_t ia[W];
     bool on[W];
     cplx<R> x[W], y[W];
-    const uint32_t d = (op.b - op.a) * P;
+    const uint32_t P = op.place, d = (op.b - op.a) * P;
 #pragma unroll
     for (uint32_t m = 0; m < W; ++m) {
         const uint32_t w = m * kTileBlock3 + threadIdx.x;
-        const uint32_t hi = w / P, lo = w - hi * P;
+        // w < 2^12: the FP32 quotient is off by at most one, which the
+        // remainder corrects
+        uint32_t hi = (uint32_t)((float)w * op.inv_place);
+        const int rr = (int)w - (int)(hi * P);
+        hi = rr < 0 ? hi - 1u : (rr >= (int)P ? hi + 1u : hi);
+        const uint32_t lo = w - hi * P;
         const uint32_t i = hi * 3u * P + op.a * P + lo;
         bool ok = w < N / 3u;
         if (ok && op.cplace != 0) {
@@ -279,16 +285,7 @@ __global__ void __launch_bounds__(kTileBlock3) k3_tile(const Tile3Args<R> A)
             const Run3Op<R> &op = A.ops[o];
             if (op.oplace != 0 && (base / op.oplace) % 3u != op.clevel)
                 continue;  // uniform over the workgroup: the condition is off for this tile
-            switch (op.pos) {  // the ion's place in the tile as a constant divisor
-            case 0: tile_pairs<R, pow3c(0), N>(t, op); break;
-            case 1: tile_pairs<R, pow3c(1), N>(t, op); break;
-            case 2: tile_pairs<R, pow3c(2), N>(t, op); break;
-            case 3: tile_pairs<R, pow3c(3), N>(t, op); break;
-            case 4: tile_pairs<R, pow3c(4), N>(t, op); break;
-            case 5: tile_pairs<R, pow3c(5), N>(t, op); break;
-            case 6: tile_pairs<R, pow3c(6), N>(t, op); break;
-            default: if constexpr (K > 7) tile_pairs<R, pow3c(7), N>(t, op); break;
-            }
+            tile_pairs<R, N>(t, op);
             __syncthreads();
         }
 #pragma unroll 8
@@ -666,6 +663,7 @@ hipError_t launch_run(qsim3_state *s, const Xform *x, size_t n, const std::vecto
         Run3Op<R> &op = A.ops[i];
         op.pos = (uint32_t)pos_of[x[i].ion];
         op.place = pow3c((int)op.pos);
+        op.inv_place = 1.0f / (float)op.place;
         op.a = (uint32_t)x[i].a;
         op.b = (uint32_t)x[i].b;
         op.mode = x[i].mode;
