@@ -601,15 +601,6 @@ OpUse op_use(const Op &op)
     return {diag ? 0ull : t, op.cmask | op.zdep | (diag ? t : 0ull)};
 }
 
-// Partition ops[lo, hi) into fused passes, appending the operations to
-// `order` pass by pass.  A pass starts with the low qubits in its tile set
-// and scans the operations not yet placed, in stream order: it takes an
-// operation when the operation commutes with every earlier one still left
-// behind and its target is in the tile set or the set has room for it
-// (diagonal operations without controls never constrain the set).  In-order
-// mode stops the scan at the first operation it cannot take instead, so
-// passes are runs of the stream.  Every pass takes at least the first
-// operation left (it commutes with nothing earlier and the set has room).
 // Reorder the operations of one fused pass, order[first, first + count), so
 // that they fall into few register groups (each group is one LDS
 // re-partition of the tile): repeatedly take, in order, every operation that
@@ -654,6 +645,103 @@ void cluster_pass(const std::vector<Op> &ops, std::vector<uint32_t> &order, size
     std::copy(out.begin(), out.end(), order.begin() + (std::ptrdiff_t)first);
 }
 
+// Operations the scan below would take into a pass with the fixed tile set
+// S, over a window of the operations left (at most `cap`).
+struct ScanOp {
+    uint64_t x, z, t;  // t: the target's bit where it must lie in the tile, else 0
+};
+
+size_t scan_count(const std::vector<ScanOp> &w, uint64_t S, size_t cap)
+{
+    uint64_t bx = 0, bz = 0;
+    size_t n = 0;
+    for (const ScanOp &u : w) {
+        if (n < cap && (u.x & (bx | bz)) == 0 && (u.z & bx) == 0 && (u.t & ~S) == 0) {
+            ++n;
+        } else {
+            bx |= u.x;
+            bz |= u.z;
+        }
+    }
+    return n;
+}
+
+// Tile set of the next fused pass in reorder mode.  Taking targets first
+// come, first served fills the set with qubits of operations that are
+// blocked soon after; instead the set grows one qubit at a time by the
+// qubit that lets the scan take the most operations of the next kWindow,
+// and then up to kMaxExchanges single exchanges of a chosen qubit for
+// another candidate are made while each takes more.  The scan itself is
+// unchanged, so any set gives a valid pass; this only picks a set that
+// carries more operations, i.e. fewer passes over the state (the 1000-gate
+// random circuits at 30 qubits: 30-33 passes instead of 36-39, for about
+// 3 ms of host time per 1000 gates).
+constexpr size_t kWindow = 64;
+constexpr int kMaxExchanges = 4;
+
+uint64_t choose_tile_set(const std::vector<Op> &ops, const std::vector<uint32_t> &rem,
+                         uint64_t S0, int k, size_t cap)
+{
+    const size_t W = std::min(rem.size(), kWindow);
+    std::vector<ScanOp> w(W);
+    uint64_t cand = 0;
+    for (size_t i = 0; i < W; ++i) {
+        const Op &op = ops[rem[i]];
+        const OpUse u = op_use(op);
+        const uint64_t t = needs_tile_target(op) ? (1ull << op.target) : 0ull;
+        w[i] = {u.x, u.z, t};
+        cand |= t;
+    }
+    cand &= ~S0;
+    uint64_t S = S0;
+    size_t best = scan_count(w, S, cap);
+    while (__builtin_popcountll(S) < k && (cand & ~S) != 0) {
+        uint64_t pick = 0;
+        size_t pc = 0;
+        for (uint64_t m = cand & ~S; m != 0; m &= m - 1) {
+            const uint64_t b = m & (~m + 1);
+            const size_t c = scan_count(w, S | b, cap);
+            if (pick == 0 || c > pc) {
+                pick = b;
+                pc = c;
+            }
+        }
+        S |= pick;
+        best = pc;
+    }
+    for (int moves = 0; moves < kMaxExchanges; ++moves) {
+        bool better = false;
+        for (uint64_t a = S & ~S0; a != 0 && !better; a &= a - 1) {
+            const uint64_t ba = a & (~a + 1);
+            for (uint64_t m = cand & ~S; m != 0; m &= m - 1) {
+                const uint64_t bb = m & (~m + 1);
+                const uint64_t T = (S & ~ba) | bb;
+                const size_t c = scan_count(w, T, cap);
+                if (c > best) {
+                    S = T;
+                    best = c;
+                    better = true;
+                    break;
+                }
+            }
+        }
+        if (!better)
+            break;
+    }
+    return S;
+}
+
+// Partition ops[lo, hi) into fused passes, appending the operations to
+// `order` pass by pass.  A pass starts with the low qubits in its tile set
+// (plus, in reorder mode, the qubits choose_tile_set picks) and scans the
+// operations not yet placed, in stream order: it takes an operation when the
+// operation commutes with every earlier one still left behind and its target
+// is in the tile set or the set has room for it (diagonal operations without
+// controls never constrain the set).  In-order mode stops the scan at the
+// first operation it cannot take instead, so passes are runs of the stream.
+// Every pass takes at least one operation: the first one left commutes with
+// nothing earlier, and either the set has room for its target or the set was
+// chosen to take something from the window.
 void schedule_fused(const qsim_state *s, const std::vector<Op> &ops, size_t lo, size_t hi, int k,
                     int G, bool reorder, std::vector<uint32_t> &order,
                     std::vector<PassPlan> &plan)
@@ -665,7 +753,9 @@ void schedule_fused(const qsim_state *s, const std::vector<Op> &ops, size_t lo, 
         rem.push_back((uint32_t)i);
     while (!rem.empty()) {
         uint64_t S = (low >= 64) ? ~0ull : ((1ull << low) - 1);
-        int size = low;
+        if (reorder)
+            S = choose_tile_set(ops, rem, S, k, cap);
+        int size = __builtin_popcountll(S);
         uint64_t bx = 0, bz = 0;  // qubits held by operations left behind
         const size_t first = order.size();
         size_t taken = 0;
