@@ -307,7 +307,18 @@ __device__ __forceinline__ void apply_op(const TileOp<R> &op, cplx<R> (&x)[1 << 
         useF = true;
         return;
     }
-    if (op.qc == 0) {
+    // Controls on lane bits: where they fall on bits that are constant over
+    // the wave (the wave bits of the thread index), every lane agrees, and
+    // the wave either skips the operation or applies its plain form.
+    bool act = true, mixed = false;
+    if (op.qc != 0) {
+        act = (j0 & op.qc) == op.qc;
+        const uint64_t agree = __builtin_amdgcn_ballot_w64(act);
+        if (agree == 0)
+            return;
+        mixed = agree != ~0ull;
+    }
+    if (!mixed) {
         switch (op.gpos) {
         case 0: apply_at<R, G, 0>(op, x); break;
         case 1: apply_at<R, G, 1>(op, x); break;
@@ -316,7 +327,6 @@ __device__ __forceinline__ void apply_op(const TileOp<R> &op, cplx<R> (&x)[1 << 
         default: if constexpr (G > 4) apply_at<R, G, 4>(op, x); break;
         }
     } else {
-        const bool act = (j0 & op.qc) == op.qc;
         switch (op.gpos) {
         case 0: apply_at_lane<R, G, 0>(op, act, x); break;
         case 1: apply_at_lane<R, G, 1>(op, act, x); break;
