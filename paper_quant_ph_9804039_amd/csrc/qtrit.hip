@@ -152,8 +152,10 @@ __host__ __device__ constexpr uint32_t pow3c(int e) { return e <= 0 ? 1u : 3u * 
 template <typename R>
 struct Run3Op {
     cplx<R> u[4];        // u00 u01 u10 u11 (kPairMat)
-    uint32_t pos;        // tile position of the ion
-    uint32_t place;      // 3^pos (inside the tile)
+    uint32_t step;       // kTileBlock3 = dh * place + dl, as dh | dl << 16: how the
+                         // (hi, lo) split of a pair number moves from one of a
+                         // thread's pairs to its next
+    uint32_t place;      // 3^(tile position of the ion)
     uint32_t a, b;       // levels, a < b
     uint32_t mode;       // PairMode
     uint32_t cplace;     // condition ion inside the tile: 3^its position, else 0
@@ -188,15 +190,27 @@ __device__ __forceinline__ void tile_pairs(cplx<R> *t, const Run3Op<R> &op)
     bool on[W];
     cplx<R> x[W], y[W];
     const uint32_t P = op.place, d = (op.b - op.a) * P;
+    const uint32_t dh = op.step & 0xFFFFu, dl = op.step >> 16;
+    // pair w = hi * P + lo sits at i = hi * 3P + a * P + lo; the thread's
+    // first pair by a quotient (w < 512: the FP32 quotient is off by at most
+    // one, which the remainder corrects), the others by stepping w by 512
+    uint32_t hi = (uint32_t)((float)threadIdx.x * op.inv_place);
+    {
+        const int rr = (int)threadIdx.x - (int)(hi * P);
+        hi = rr < 0 ? hi - 1u : (rr >= (int)P ? hi + 1u : hi);
+    }
+    uint32_t lo = threadIdx.x - hi * P;
 #pragma unroll
     for (uint32_t m = 0; m < W; ++m) {
         const uint32_t w = m * kTileBlock3 + threadIdx.x;
-        // w < 2^12: the FP32 quotient is off by at most one, which the
-        // remainder corrects
-        uint32_t hi = (uint32_t)((float)w * op.inv_place);
-        const int rr = (int)w - (int)(hi * P);
-        hi = rr < 0 ? hi - 1u : (rr >= (int)P ? hi + 1u : hi);
-        const uint32_t lo = w - hi * P;
+        if (m > 0) {
+            lo += dl;
+            hi += dh;
+            if (lo >= P) {
+                lo -= P;
+                ++hi;
+            }
+        }
         const uint32_t i = hi * 3u * P + op.a * P + lo;
         bool ok = w < N / 3u;
         if (ok && op.cplace != 0) {
@@ -661,8 +675,8 @@ hipError_t launch_run(qsim3_state *s, const Xform *x, size_t n, const std::vecto
     A.nops = (uint32_t)n;
     for (size_t i = 0; i < n; ++i) {
         Run3Op<R> &op = A.ops[i];
-        op.pos = (uint32_t)pos_of[x[i].ion];
-        op.place = pow3c((int)op.pos);
+        op.place = pow3c(pos_of[x[i].ion]);
+        op.step = (uint32_t)kTileBlock3 / op.place | ((uint32_t)kTileBlock3 % op.place) << 16;
         op.inv_place = 1.0f / (float)op.place;
         op.a = (uint32_t)x[i].a;
         op.b = (uint32_t)x[i].b;
