@@ -430,9 +430,12 @@ typedef struct {
 } qsim3_pulse;
 
 /* Register of num_ions (1..20) ions in dtype, set to |0...0>; the options
- * used are device, hip_stream and exec_mode (1: one launch per
- * transformation; otherwise runs of transformations whose ions fit one LDS
- * tile are applied as fused passes, on registers larger than a tile).
+ * used are device, hip_stream and exec_mode.  On registers larger than one
+ * LDS tile, transformations are applied as fused passes over tiles of ions:
+ * exec_mode 0 (default) lets a pass take a transformation from further down
+ * the stream when it commutes with every earlier one left behind (different
+ * ions, neither acting on the other's condition ion), exec_mode 2 takes runs
+ * of the stream in order; exec_mode 1 launches once per transformation.
  * EINVAL / ENOMEM as qsim_create. */
 int qsim3_create(int num_ions, int dtype, const qsim_options *opt, qsim3_state **out);
 int qsim3_destroy(qsim3_state *s);

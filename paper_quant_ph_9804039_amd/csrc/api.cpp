@@ -15,6 +15,7 @@
 #include "common.h"
 #include "internal.h"
 #include "launch.h"
+#include "lookahead.h"
 #include "qsim.h"
 
 using namespace qsim;
@@ -645,37 +646,11 @@ void cluster_pass(const std::vector<Op> &ops, std::vector<uint32_t> &order, size
     std::copy(out.begin(), out.end(), order.begin() + (std::ptrdiff_t)first);
 }
 
-// Operations the scan below would take into a pass with the fixed tile set
-// S, over a window of the operations left (at most `cap`).
-struct ScanOp {
-    uint64_t x, z, t;  // t: the target's bit where it must lie in the tile, else 0
-};
-
-size_t scan_count(const std::vector<ScanOp> &w, uint64_t S, size_t cap)
-{
-    uint64_t bx = 0, bz = 0;
-    size_t n = 0;
-    for (const ScanOp &u : w) {
-        if (n < cap && (u.x & (bx | bz)) == 0 && (u.z & bx) == 0 && (u.t & ~S) == 0) {
-            ++n;
-        } else {
-            bx |= u.x;
-            bz |= u.z;
-        }
-    }
-    return n;
-}
-
-// Tile set of the next fused pass in reorder mode.  Taking targets first
-// come, first served fills the set with qubits of operations that are
-// blocked soon after; instead the set grows one qubit at a time by the
-// qubit that lets the scan take the most operations of the next kWindow,
-// and then up to kMaxExchanges single exchanges of a chosen qubit for
-// another candidate are made while each takes more.  The scan itself is
-// unchanged, so any set gives a valid pass; this only picks a set that
-// carries more operations, i.e. fewer passes over the state (the 1000-gate
-// random circuits at 30 qubits: 30-33 passes instead of 36-39, for about
-// 3 ms of host time per 1000 gates).
+// Tile set of the next fused pass in reorder mode, by lookahead over the
+// next kWindow operations with up to kMaxExchanges exchanges (the 1000-gate
+// random circuits at 30 qubits: 30-33 passes instead of 36-39 with sets
+// filled first come, first served, for about 3 ms of host time per 1000
+// gates).
 constexpr size_t kWindow = 64;
 constexpr int kMaxExchanges = 4;
 
@@ -684,51 +659,12 @@ uint64_t choose_tile_set(const std::vector<Op> &ops, const std::vector<uint32_t>
 {
     const size_t W = std::min(rem.size(), kWindow);
     std::vector<ScanOp> w(W);
-    uint64_t cand = 0;
     for (size_t i = 0; i < W; ++i) {
         const Op &op = ops[rem[i]];
         const OpUse u = op_use(op);
-        const uint64_t t = needs_tile_target(op) ? (1ull << op.target) : 0ull;
-        w[i] = {u.x, u.z, t};
-        cand |= t;
+        w[i] = {u.x, u.z, needs_tile_target(op) ? (1ull << op.target) : 0ull};
     }
-    cand &= ~S0;
-    uint64_t S = S0;
-    size_t best = scan_count(w, S, cap);
-    while (__builtin_popcountll(S) < k && (cand & ~S) != 0) {
-        uint64_t pick = 0;
-        size_t pc = 0;
-        for (uint64_t m = cand & ~S; m != 0; m &= m - 1) {
-            const uint64_t b = m & (~m + 1);
-            const size_t c = scan_count(w, S | b, cap);
-            if (pick == 0 || c > pc) {
-                pick = b;
-                pc = c;
-            }
-        }
-        S |= pick;
-        best = pc;
-    }
-    for (int moves = 0; moves < kMaxExchanges; ++moves) {
-        bool better = false;
-        for (uint64_t a = S & ~S0; a != 0 && !better; a &= a - 1) {
-            const uint64_t ba = a & (~a + 1);
-            for (uint64_t m = cand & ~S; m != 0; m &= m - 1) {
-                const uint64_t bb = m & (~m + 1);
-                const uint64_t T = (S & ~ba) | bb;
-                const size_t c = scan_count(w, T, cap);
-                if (c > best) {
-                    S = T;
-                    best = c;
-                    better = true;
-                    break;
-                }
-            }
-        }
-        if (!better)
-            break;
-    }
-    return S;
+    return lookahead_set(w, S0, k, cap, kMaxExchanges);
 }
 
 // Partition ops[lo, hi) into fused passes, appending the operations to

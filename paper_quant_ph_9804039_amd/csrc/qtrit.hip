@@ -38,6 +38,7 @@
 
 #include "common.h"
 #include "internal.h"
+#include "lookahead.h"
 #include "qsim.h"
 
 namespace {
@@ -583,6 +584,7 @@ struct qsim3_state {
     uint64_t pulses = 0;
     uint64_t launches = 0;   // state kernel launches (fused passes or per transformation)
     bool per_pulse = false;  // exec_mode 1: one launch per transformation
+    bool in_order = false;   // exec_mode 2: fused passes over runs of the stream
 };
 
 namespace {
@@ -701,9 +703,44 @@ hipError_t launch_run(qsim3_state *s, const Xform *x, size_t n, const std::vecto
     return hipGetLastError();
 }
 
-// Apply transformations in order: fused passes over runs whose ions fit one
-// tile (registers larger than a tile, exec_mode other than 1), else one
-// launch each.
+// Fused passes over the tile ions T (K ions, the lowest always among them).
+// Two transformations commute when they act on different ions and neither
+// acts on the ion the other is conditioned on (a condition only reads its
+// ion's level), so a pass may take a transformation from further down the
+// stream when it commutes with every earlier one left behind: exact up to
+// rounding, and it lets one HBM pass carry several gates' worth of
+// transformations.  T is chosen by lookahead (the same rule as the two-level
+// passes); in-order mode (exec_mode 2) takes runs of the stream instead.
+constexpr size_t kWindow3 = 64;
+constexpr int kMaxExchanges3 = 4;
+
+template <typename R>
+int launch_ions(qsim3_state *s, const Xform *x, size_t n, uint32_t in)
+{
+    const int K = kTileIons3<R>;
+    int nin = __builtin_popcount(in);
+    // fill T to K ions with the lowest ions not yet in it
+    for (int q = 0; q < s->M && nin < K; ++q)
+        if (!(in & (1u << q))) {
+            in |= 1u << q;
+            ++nin;
+        }
+    std::vector<int> T;
+    for (int q = 0; q < s->M; ++q)
+        if (in & (1u << q))
+            T.push_back(q);
+    HIP3(launch_run<R>(s, x, n, T), "fused pass");
+    ++s->launches;
+    return QSIM_OK;
+}
+
+int launch_ions_any(qsim3_state *s, const Xform *x, size_t n, uint32_t in)
+{
+    return s->dtype == QSIM_C64 ? launch_ions<float>(s, x, n, in) : launch_ions<double>(s, x, n, in);
+}
+
+// Apply transformations: fused passes on registers larger than a tile
+// (exec_mode other than 1), else one launch each in stream order.
 int apply_xforms(qsim3_state *s, const std::vector<Xform> &xs)
 {
     const int K = s->dtype == QSIM_C64 ? kTileIons3<float> : kTileIons3<double>;
@@ -715,36 +752,75 @@ int apply_xforms(qsim3_state *s, const std::vector<Xform> &xs)
         }
         return QSIM_OK;
     }
-    size_t i = 0;
-    while (i < xs.size()) {
-        uint32_t in = (1u << kLowIons3) - 1;  // ions of T
-        int nin = (int)kLowIons3;
-        size_t j = i;
-        for (; j < xs.size() && j - i < cap; ++j) {
-            const uint32_t bit = 1u << xs[j].ion;
-            if (!(in & bit)) {
-                if (nin == K)
-                    break;
-                in |= bit;
-                ++nin;
+    const uint32_t low = (1u << kLowIons3) - 1;
+    if (s->in_order) {
+        size_t i = 0;
+        while (i < xs.size()) {
+            uint32_t in = low;
+            int nin = (int)kLowIons3;
+            size_t j = i;
+            for (; j < xs.size() && j - i < cap; ++j) {
+                const uint32_t bit = 1u << xs[j].ion;
+                if (!(in & bit)) {
+                    if (nin == K)
+                        break;
+                    in |= bit;
+                    ++nin;
+                }
+            }
+            const int rc = launch_ions_any(s, &xs[i], j - i, in);
+            if (rc != QSIM_OK)
+                return rc;
+            i = j;
+        }
+        return QSIM_OK;
+    }
+    std::vector<qsim::ScanOp> all(xs.size());
+    for (size_t i = 0; i < xs.size(); ++i) {
+        const uint64_t t = 1ull << xs[i].ion;
+        all[i] = {t, xs[i].cion >= 0 ? (1ull << xs[i].cion) : 0ull, t};
+    }
+    std::vector<uint32_t> rem(xs.size()), left;
+    for (size_t i = 0; i < xs.size(); ++i)
+        rem[i] = (uint32_t)i;
+    std::vector<qsim::ScanOp> w;
+    std::vector<Xform> run;
+    while (!rem.empty()) {
+        w.clear();
+        for (size_t i = 0; i < rem.size() && i < kWindow3; ++i)
+            w.push_back(all[rem[i]]);
+        uint64_t in = qsim::lookahead_set(w, low, K, cap, kMaxExchanges3);
+        int nin = __builtin_popcountll(in);
+        uint64_t bx = 0, bz = 0;
+        run.clear();
+        left.clear();
+        for (const uint32_t r : rem) {
+            const qsim::ScanOp &u = all[r];
+            bool ok = run.size() < cap && (u.x & (bx | bz)) == 0 && (u.z & bx) == 0;
+            if (ok && !(in & u.t)) {
+                if (nin == K) {
+                    ok = false;
+                } else {
+                    in |= u.t;
+                    ++nin;
+                }
+            }
+            if (ok) {
+                run.push_back(xs[r]);
+            } else {
+                left.push_back(r);
+                bx |= u.x;
+                bz |= u.z;
             }
         }
-        // fill T to K ions with the lowest ions not yet in it
-        for (int q = 0; q < s->M && nin < K; ++q)
-            if (!(in & (1u << q))) {
-                in |= 1u << q;
-                ++nin;
-            }
-        std::vector<int> T;
-        for (int q = 0; q < s->M; ++q)
-            if (in & (1u << q))
-                T.push_back(q);
-        if (s->dtype == QSIM_C64)
-            HIP3(launch_run<float>(s, &xs[i], j - i, T), "fused pass");
-        else
-            HIP3(launch_run<double>(s, &xs[i], j - i, T), "fused pass");
-        ++s->launches;
-        i = j;
+        // the first transformation left commutes with nothing before it and
+        // the window's best set takes at least one, so every pass does work
+        if (run.empty())
+            return qsim::set_error(QSIM_EDEVICE, "three-state scheduler: internal error (empty pass)");
+        const int rc = launch_ions_any(s, run.data(), run.size(), (uint32_t)in);
+        if (rc != QSIM_OK)
+            return rc;
+        rem.swap(left);
     }
     return QSIM_OK;
 }
@@ -829,6 +905,7 @@ int qsim3_create(int num_ions, int dtype, const qsim_options *opt, qsim3_state *
         s->device = o.device;
         s->n = pow3(num_ions);
         s->per_pulse = o.exec_mode == 1;
+        s->in_order = o.exec_mode == 2;
         e = hipSetDevice(o.device);
         if (e == hipSuccess) {
             if (o.hip_stream) {

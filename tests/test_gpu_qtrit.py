@@ -171,16 +171,18 @@ def test_largest_register_cnot_and_x_on_basis_states():
 def test_fused_passes_vs_oracle_and_per_transformation_path(dtype, M, seed):
     """Registers larger than one tile (3^8 complex64 / 3^7 complex128
     amplitudes) run fused passes: against the oracle with errors and flips,
-    and against one launch per transformation (exec_mode 1), which does the
-    same operations on each pair (the compiler may contract them into FMAs
-    differently, so the two agree to rounding, not bit for bit)."""
+    against one launch per transformation (exec_mode 1), which does the same
+    operations on each pair (the compiler may contract them into FMAs
+    differently, so the two agree to rounding, not bit for bit), and against
+    fused passes over runs of the stream in order (exec_mode 2): the default
+    passes take commuting transformations from further down the stream."""
     print(f"three-state fused M={M} dtype={dtype}", flush=True)
     g = cg.random_circuit(M, 90, 500 + seed, kinds=KINDS)
     em = oracle.Errors(sigma=0.03, p_bitflip=0.01, p_phaseflip=0.01, seed=seed, trial=2)
     ref = oracle.as_complex(oracle.simulate3(M, g, em))
-    out = []
+    out, launches = [], []
     npulses = len(q.qsim3_lower(g, M))
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         with q.State3(M, dtype, q.make_options(exec_mode=mode)) as s:
             s.inject_errors(em.sigma, em.p_bitflip, em.p_phaseflip, em.seed, em.trial)
             s.apply(g[:40])
@@ -188,11 +190,14 @@ def test_fused_passes_vs_oracle_and_per_transformation_path(dtype, M, seed):
             out.append(s.amplitudes())
             info = s.info()
             assert info["transformations"] == npulses
-            # fused: a few runs; per transformation: one launch each (flips too)
-            assert (info["launches"] < npulses // 3) if mode == 0 else (info["launches"] >= npulses)
-    assert np.max(np.abs(out[0] - ref)) <= TOL[dtype]
-    assert np.max(np.abs(out[1] - ref)) <= TOL[dtype]
+            launches.append(info["launches"])
+            # fused: a few passes; per transformation: one launch each (flips too)
+            assert (info["launches"] >= npulses) if mode == 1 else (info["launches"] < npulses // 3)
+    assert launches[0] <= launches[2]
+    for o in out:
+        assert np.max(np.abs(o - ref)) <= TOL[dtype]
     assert np.max(np.abs(out[0] - out[1])) <= TOL[dtype]
+    assert np.max(np.abs(out[2] - out[1])) <= TOL[dtype]
 
 
 def test_fused_conditional_transformations_inside_and_outside_the_tile():
@@ -218,7 +223,8 @@ def test_fused_conditional_transformations_inside_and_outside_the_tile():
                 "theta": 0.7, "phi": -0.2 * q_} for q_ in range(M)]
     for p in spread + pulses:
         oracle.apply_pulse3(psi, M, p)
-    with q.State3(M, q.QSIM_C128) as s:
-        s.reset(5)
-        s.apply_pulses(spread + pulses)
-        assert np.max(np.abs(s.amplitudes() - oracle.as_complex(psi))) < 1e-12
+    for mode in (0, 2):
+        with q.State3(M, q.QSIM_C128, q.make_options(exec_mode=mode)) as s:
+            s.reset(5)
+            s.apply_pulses(spread + pulses)
+            assert np.max(np.abs(s.amplitudes() - oracle.as_complex(psi))) < 1e-12
