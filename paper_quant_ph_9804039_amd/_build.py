@@ -41,8 +41,8 @@ def sources():
                   if f.endswith((".hip", ".cpp")))
 
 
-# The fused tile pass and the Monte Carlo register-group kernel dispatch on
-# a uniform operation stream: leaving
+# The fused tile passes (two- and three-level) and the Monte Carlo
+# register-group kernel dispatch on a uniform operation stream: leaving
 # uniform branch regions unstructurized keeps the register quantum in place
 # across the dispatch instead of copying it through the structurizer's flow
 # blocks.
@@ -50,6 +50,7 @@ FILE_FLAGS = {
     "kernels_tile_c64.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"],
     "kernels_tile_c128.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"],
     "kernels_trials.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"],
+    "qtrit.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"],
 }
 
 

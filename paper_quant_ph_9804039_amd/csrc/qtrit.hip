@@ -135,12 +135,20 @@ __global__ void __launch_bounds__(kBlock3) k3_init(cplx<R> *psi, uint32_t n, uin
 // A transformation only mixes amplitudes that differ in its ion's level, so
 // for a set T of k ions the 3^k amplitudes that share the levels of every
 // ion outside T (a tile) are closed under every transformation on an ion of
-// T, and a condition on an ion outside T is a constant of the tile.  A run
-// of transformations whose ions lie in T is applied tile by tile: a
-// workgroup loads the tile into LDS, applies the run in order (a barrier
-// between transformations), and writes the tile back: one HBM read and
-// write for the whole run instead of one per transformation.  T always holds
-// the lowest ions, so a tile is runs of 3^low contiguous amplitudes.
+// T, and a condition on an ion outside T is a constant of the tile.  A pass
+// applies a run of transformations whose ions lie in T tile by tile: a
+// workgroup loads the tile into LDS, applies the run, and writes the tile
+// back: one HBM read and write for the whole run instead of one per
+// transformation.  T always holds the lowest ions, so a tile is runs of
+// 3^low contiguous amplitudes.
+//
+// Inside the tile the run comes in groups of transformations on at most two
+// tile ions A, B.  For a group each thread holds one register quantum: the 9
+// amplitudes that share the levels of every other tile ion, register
+// ra + 3 rb holding A at level ra and B at level rb.  A transformation of the
+// group is then three register pairs (one where it is conditioned on the
+// other group ion), with no LDS traffic and no barrier; the tile passes
+// through LDS once per group instead of once per transformation.
 
 constexpr uint32_t kLowIons3 = 3;
 template <typename R>
@@ -150,21 +158,27 @@ constexpr int kMaxRun3 = sizeof(R) == 4 ? 48 : 36;   // transformations per pass
 
 __host__ __device__ constexpr uint32_t pow3c(int e) { return e <= 0 ? 1u : 3u * pow3c(e - 1); }
 
+// One thread per register quantum: 3^(k-2) quanta (729 complex64, 243 complex128).
+template <typename R>
+constexpr uint32_t kTileBlock3 = sizeof(R) == 4 ? 768u : 256u;
+
 template <typename R>
 struct Run3Op {
     cplx<R> u[4];        // u00 u01 u10 u11 (kPairMat)
-    uint32_t step;       // kTileBlock3 = dh * place + dl, as dh | dl << 16: how the
-                         // (hi, lo) split of a pair number moves from one of a
-                         // thread's pairs to its next
     uint32_t place;      // 3^(tile position of the ion)
     uint32_t a, b;       // levels, a < b
     uint32_t mode;       // PairMode
-    uint32_t cplace;     // condition ion inside the tile: 3^its position, else 0
+    uint32_t cplace;     // condition ion inside the tile but outside the group: 3^its position, else 0
     uint32_t oplace;     // condition ion outside the tile: 3^ion, else 0
     uint32_t clevel;
+    uint32_t shape;      // in its group: ion slot (0: A, 1: B) | level pair (0: 0-1, 1: 0-2,
+                         // 2: 1-2) << 1 | conditioned on the other group ion << 3
     float inv_cplace;    // 1 / cplace
-    float inv_place;     // 1 / place
 };
+
+// Group word: first transformation (6 bits), count (6 bits), tile positions
+// of A and B (4 bits each).
+constexpr uint32_t kGroup3Count = 6, kGroup3A = 12, kGroup3B = 16;
 
 template <typename R>
 struct Tile3Args {
@@ -172,93 +186,123 @@ struct Tile3Args {
     uint32_t ntiles;            // 3^(M - k)
     uint32_t nout;              // ions outside the tile
     uint32_t nops;
+    uint32_t ngroups;
     uint32_t tplace[kMaxIons];  // 3^ion of tile positions 0..k-1 (positions < low: ion = position)
     uint32_t oplace[kMaxIons];  // 3^ion of the ions outside the tile, ascending
+    uint32_t group[kMaxRun3<R>];
     Run3Op<R> ops[kMaxRun3<R>];
 };
-
-constexpr int kTileBlock3 = 512;
-
-// One transformation on the tile in LDS: pair w of the N / 3 pairs of levels
-// a, b of the ion at tile place P.  Each thread takes its pairs w = tid,
-// tid + 512, ... all at once (the pairs are disjoint), so their LDS reads are
-// in flight together.
-template <typename R, uint32_t N>
-__device__ __forceinline__ void tile_pairs(cplx<R> *t, const Run3Op<R> &op)
-{
-    constexpr uint32_t W = (N / 3u + kTileBlock3 - 1) / kTileBlock3;
-    uint32_t ia[W];
-    bool on[W];
-    cplx<R> x[W], y[W];
-    const uint32_t P = op.place, d = (op.b - op.a) * P;
-    const uint32_t dh = op.step & 0xFFFFu, dl = op.step >> 16;
-    // pair w = hi * P + lo sits at i = hi * 3P + a * P + lo; the thread's
-    // first pair by a quotient (w < 512: the FP32 quotient is off by at most
-    // one, which the remainder corrects), the others by stepping w by 512
-    uint32_t hi = (uint32_t)((float)threadIdx.x * op.inv_place);
-    {
-        const int rr = (int)threadIdx.x - (int)(hi * P);
-        hi = rr < 0 ? hi - 1u : (rr >= (int)P ? hi + 1u : hi);
-    }
-    uint32_t lo = threadIdx.x - hi * P;
-#pragma unroll
-    for (uint32_t m = 0; m < W; ++m) {
-        const uint32_t w = m * kTileBlock3 + threadIdx.x;
-        if (m > 0) {
-            lo += dl;
-            hi += dh;
-            if (lo >= P) {
-                lo -= P;
-                ++hi;
-            }
-        }
-        const uint32_t i = hi * 3u * P + op.a * P + lo;
-        bool ok = w < N / 3u;
-        if (ok && op.cplace != 0) {
-            // i < 3^8: the FP32 quotient is off by at most one, which the
-            // remainder corrects
-            uint32_t q = (uint32_t)((float)i * op.inv_cplace);
-            const int r = (int)i - (int)(q * op.cplace);
-            q = r < 0 ? q - 1u : (r >= (int)op.cplace ? q + 1u : q);
-            ok = q - 3u * (q / 3u) == op.clevel;
-        }
-        ia[m] = i;
-        on[m] = ok;
-        if (ok) {
-            x[m] = t[i];
-            y[m] = t[i + d];
-        }
-    }
-#pragma unroll
-    for (uint32_t m = 0; m < W; ++m) {
-        if (!on[m])
-            continue;
-        const uint32_t i = ia[m];
-        if (op.mode == kPairSwap) {
-            t[i] = y[m];
-            t[i + d] = x[m];
-        } else if (op.mode == kPairNegB) {
-            t[i + d] = {-y[m].re, -y[m].im};
-        } else {
-            t[i] = qsim::cmad2(op.u[0], x[m], op.u[1], y[m]);
-            t[i + d] = qsim::cmad2(op.u[2], x[m], op.u[3], y[m]);
-        }
-    }
-}
 
 static_assert(sizeof(Tile3Args<float>) <= 4096 && sizeof(Tile3Args<double>) <= 4096,
               "kernel arguments must fit 4 KiB");
 
+// The pairs of one transformation in a quantum: ion slot S, levels LA < LB.
+// C: conditioned on the other group ion (only its level clevel moves);
+// W: conditioned on a tile ion outside the group, which `act` holds for this
+// thread (applied everywhere with the identity where act is false, so no
+// lane branches).
+template <typename R, int S, int LA, int LB, bool W>
+__device__ __forceinline__ void quantum_pairs(const Run3Op<R> &op, bool C, bool act, cplx<R> (&x)[9])
+{
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+        if (C && (uint32_t)o != op.clevel)
+            continue;
+        const int i = S == 0 ? LA + 3 * o : o + 3 * LA;
+        const int j = S == 0 ? LB + 3 * o : o + 3 * LB;
+        const cplx<R> p = x[i], q = x[j];
+        if (op.mode == kPairSwap) {
+            const bool s = !W || act;
+            x[i] = {s ? q.re : p.re, s ? q.im : p.im};
+            x[j] = {s ? p.re : q.re, s ? p.im : q.im};
+        } else if (op.mode == kPairNegB) {
+            const bool s = !W || act;
+            x[j] = {s ? -q.re : q.re, s ? -q.im : q.im};
+        } else if (W) {
+            const R one = R(1), zero = R(0);
+            const cplx<R> u0 = {act ? op.u[0].re : one, act ? op.u[0].im : zero};
+            const cplx<R> u1 = {act ? op.u[1].re : zero, act ? op.u[1].im : zero};
+            const cplx<R> u2 = {act ? op.u[2].re : zero, act ? op.u[2].im : zero};
+            const cplx<R> u3 = {act ? op.u[3].re : one, act ? op.u[3].im : zero};
+            x[i] = qsim::cmad2(u0, p, u1, q);
+            x[j] = qsim::cmad2(u2, p, u3, q);
+        } else {
+            x[i] = qsim::cmad2(op.u[0], p, op.u[1], q);
+            x[j] = qsim::cmad2(op.u[2], p, op.u[3], q);
+        }
+    }
+}
+
+template <typename R, bool W>
+__device__ __forceinline__ void quantum_op(const Run3Op<R> &op, bool act, cplx<R> (&x)[9])
+{
+    const bool C = (op.shape >> 3) & 1u;
+    switch (op.shape & 7u) {
+    case 0: quantum_pairs<R, 0, 0, 1, W>(op, C, act, x); break;
+    case 1: quantum_pairs<R, 1, 0, 1, W>(op, C, act, x); break;
+    case 2: quantum_pairs<R, 0, 0, 2, W>(op, C, act, x); break;
+    case 3: quantum_pairs<R, 1, 0, 2, W>(op, C, act, x); break;
+    case 4: quantum_pairs<R, 0, 1, 2, W>(op, C, act, x); break;
+    default: quantum_pairs<R, 1, 1, 2, W>(op, C, act, x); break;
+    }
+}
+
+// Powers of three, read with uniform indices (scalar loads).
+__constant__ uint32_t c_pow3[16] = {1u, 3u, 9u, 27u, 81u, 243u, 729u, 2187u, 6561u, 19683u,
+                                    59049u, 177147u, 531441u, 1594323u, 4782969u, 14348907u};
+
+// One transformation of a group on the thread's quantum (bt: tile index of
+// its register 0).
 template <typename R>
-__global__ void __launch_bounds__(kTileBlock3) k3_tile(const Tile3Args<R> A)
+__device__ __forceinline__ void group_op(const Run3Op<R> &op, uint32_t base, uint32_t bt,
+                                         cplx<R> (&x)[9])
+{
+    if (op.oplace != 0 && (base / op.oplace) % 3u != op.clevel)
+        return;  // uniform over the workgroup: the condition is off for this tile
+    if (op.cplace == 0) {
+        quantum_op<R, false>(op, true, x);
+    } else {
+        // bt < 3^8: the FP32 quotient is off by at most one, which the
+        // remainder corrects
+        uint32_t q = (uint32_t)((float)bt * op.inv_cplace);
+        const int r = (int)bt - (int)(q * op.cplace);
+        q = r < 0 ? q - 1u : (r >= (int)op.cplace ? q + 1u : q);
+        quantum_op<R, true>(op, q - 3u * (q / 3u) == op.clevel, x);
+    }
+}
+
+// One amplitude of the LDS tile at its natural alignment (the struct only
+// promises that of its component, and the compiler then splits the access).
+__device__ __forceinline__ cplx<float> lds_get(const cplx<float> *p)
+{
+    const float2 v = *static_cast<const float2 *>(__builtin_assume_aligned(p, 8));
+    return {v.x, v.y};
+}
+__device__ __forceinline__ void lds_put(cplx<float> *p, cplx<float> a)
+{
+    *static_cast<float2 *>(__builtin_assume_aligned(p, 8)) = make_float2(a.re, a.im);
+}
+__device__ __forceinline__ cplx<double> lds_get(const cplx<double> *p)
+{
+    const double2 v = *static_cast<const double2 *>(__builtin_assume_aligned(p, 16));
+    return {v.x, v.y};
+}
+__device__ __forceinline__ void lds_put(cplx<double> *p, cplx<double> a)
+{
+    *static_cast<double2 *>(__builtin_assume_aligned(p, 16)) = make_double2(a.re, a.im);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kTileBlock3<R>) k3_tile(const Tile3Args<R> A)
 {
     constexpr int K = kTileIons3<R>;
-    constexpr uint32_t N = pow3c(K), L = pow3c(kLowIons3), H = pow3c(K - kLowIons3);
+    constexpr uint32_t T = kTileBlock3<R>;
+    constexpr uint32_t N = pow3c(K), L = pow3c(kLowIons3), H = pow3c(K - kLowIons3), NQ = N / 9u;
     __shared__ cplx<R> t[N];
     __shared__ uint32_t offhi[H];
     // offset of tile element e from the tile's base: e % L covers the low
     // ions (contiguous), offhi[e / L] the others
-    for (uint32_t h = threadIdx.x; h < H; h += kTileBlock3) {
+    for (uint32_t h = threadIdx.x; h < H; h += T) {
         uint32_t off = 0, v = h;
         for (int j = kLowIons3; j < K; ++j) {
             const uint32_t q = v / 3u;
@@ -266,6 +310,18 @@ __global__ void __launch_bounds__(kTileBlock3) k3_tile(const Tile3Args<R> A)
             v = q;
         }
         offhi[h] = off;
+    }
+    // the thread number's base-3 digits: a group places them on the tile
+    // positions other than its own two, in ascending order
+    uint32_t dig[K - 2];
+    {
+        uint32_t v = threadIdx.x < NQ ? threadIdx.x : NQ - 1u;
+#pragma unroll
+        for (int j = 0; j < K - 2; ++j) {
+            const uint32_t q = v / 3u;
+            dig[j] = v - 3u * q;
+            v = q;
+        }
     }
     __syncthreads();
     const uint32_t per = (A.ntiles + gridDim.x - 1) / gridDim.x;
@@ -278,33 +334,65 @@ __global__ void __launch_bounds__(kTileBlock3) k3_tile(const Tile3Args<R> A)
             base += (v - 3u * q) * A.oplace[m];
             v = q;
         }
-        // batches of loads in flight at once, then into LDS
-        constexpr uint32_t U = 8;
-        for (uint32_t e0 = 0; e0 < N; e0 += U * kTileBlock3) {
+        // whole batches of loads in flight at once, then into LDS; the tail
+        // element by element
+        constexpr uint32_t U = 8, NB = N / (U * T) * (U * T);
+        for (uint32_t e0 = 0; e0 < NB; e0 += U * T) {
             cplx<R> v[U];
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
-                const uint32_t e = e0 + u * kTileBlock3 + threadIdx.x;
-                if (e < N)
-                    v[u] = A.psi[base + e % L + offhi[e / L]];
+                const uint32_t e = e0 + u * T + threadIdx.x;
+                v[u] = A.psi[base + e % L + offhi[e / L]];
             }
 #pragma unroll
-            for (uint32_t u = 0; u < U; ++u) {
-                const uint32_t e = e0 + u * kTileBlock3 + threadIdx.x;
-                if (e < N)
-                    t[e] = v[u];
-            }
+            for (uint32_t u = 0; u < U; ++u)
+                t[e0 + u * T + threadIdx.x] = v[u];
         }
+#pragma unroll 8
+        for (uint32_t e = NB + threadIdx.x; e < N; e += T)
+            t[e] = A.psi[base + e % L + offhi[e / L]];
         __syncthreads();
-        for (uint32_t o = 0; o < A.nops; ++o) {
-            const Run3Op<R> &op = A.ops[o];
-            if (op.oplace != 0 && (base / op.oplace) % 3u != op.clevel)
-                continue;  // uniform over the workgroup: the condition is off for this tile
-            tile_pairs<R, N>(t, op);
+        for (uint32_t g = 0; g < A.ngroups; ++g) {
+            const uint32_t gw = A.group[g];
+            const uint32_t pa = (gw >> kGroup3A) & 15u, pb = (gw >> kGroup3B) & 15u;
+            const uint32_t first = gw & 63u, end = first + ((gw >> kGroup3Count) & 63u);
+            {
+                // tile index of register 0: digit j on the j-th tile position
+                // other than pa < pb (the places are uniform)
+                const uint32_t PA = c_pow3[pa], PB = c_pow3[pb];
+                uint32_t bt = 0;
+#pragma unroll
+                for (int j = 0; j < K - 2; ++j) {
+                    uint32_t p = (uint32_t)j;
+                    p += p >= pa ? 1u : 0u;
+                    p += p >= pb ? 1u : 0u;
+                    bt += dig[j] * c_pow3[p];
+                }
+                cplx<R> x[9];
+#pragma unroll
+                for (int r = 0; r < 9; ++r)
+                    x[r] = lds_get(t + bt + (uint32_t)(r % 3) * PA + (uint32_t)(r / 3) * PB);
+                // two transformations per trip: the second writes its results
+                // back into the registers the first read, so no copy of the
+                // quantum closes each trip
+                for (uint32_t o = first; o < end; o += 2) {
+                    group_op<R>(A.ops[o], base, bt, x);
+                    if (o + 1 >= end)
+                        break;
+                    group_op<R>(A.ops[o + 1], base, bt, x);
+                }
+                // the threads past the last quantum (complex64: 729 of 768)
+                // worked on a copy of the last one and write nothing
+                if (threadIdx.x < NQ) {
+#pragma unroll
+                    for (int r = 0; r < 9; ++r)
+                        lds_put(t + bt + (uint32_t)(r % 3) * PA + (uint32_t)(r / 3) * PB, x[r]);
+                }
+            }
             __syncthreads();
         }
 #pragma unroll 8
-        for (uint32_t e = threadIdx.x; e < N; e += kTileBlock3)
+        for (uint32_t e = threadIdx.x; e < N; e += T)
             A.psi[base + e % L + offhi[e / L]] = t[e];
         __syncthreads();
     }
@@ -656,12 +744,18 @@ Xform make_flip(int ion, uint32_t mode)
 
 // A run of transformations as one fused pass: tile ions T (the low ions,
 // then the run's ions in ascending order), the rest enumerate the tiles.
+// The run is reordered into register groups of at most two tile ions:
+// sweeps over the transformations left take, in order, each one that
+// commutes with the ones the sweep skipped and whose ion fits the group (the
+// same rule as the pass itself, so the order stays exact).
 template <typename R>
 hipError_t launch_run(qsim3_state *s, const Xform *x, size_t n, const std::vector<int> &T)
 {
     Tile3Args<R> A{};
     A.psi = static_cast<cplx<R> *>(s->psi);
     const int M = s->M, K = kTileIons3<R>;
+    if (n == 0 || n > (size_t)kMaxRun3<R>)
+        return hipErrorInvalidValue;
     int pos_of[kMaxIons];
     for (int q = 0; q < M; ++q)
         pos_of[q] = -1;
@@ -675,31 +769,81 @@ hipError_t launch_run(qsim3_state *s, const Xform *x, size_t n, const std::vecto
             A.oplace[A.nout++] = (uint32_t)pow3(q);
     A.ntiles = (uint32_t)pow3(M - K);
     A.nops = (uint32_t)n;
-    for (size_t i = 0; i < n; ++i) {
-        Run3Op<R> &op = A.ops[i];
-        op.place = pow3c(pos_of[x[i].ion]);
-        op.step = (uint32_t)kTileBlock3 / op.place | ((uint32_t)kTileBlock3 % op.place) << 16;
-        op.inv_place = 1.0f / (float)op.place;
-        op.a = (uint32_t)x[i].a;
-        op.b = (uint32_t)x[i].b;
-        op.mode = x[i].mode;
-        op.cplace = 0;
-        op.oplace = 0;
-        op.clevel = (uint32_t)x[i].clevel;
-        op.inv_cplace = 0.0f;
-        if (x[i].cion >= 0) {
-            if (pos_of[x[i].cion] >= 0) {
-                op.cplace = pow3c(pos_of[x[i].cion]);
-                op.inv_cplace = 1.0f / (float)op.cplace;
+    A.ngroups = 0;
+
+    std::vector<size_t> rem(n), left;
+    for (size_t i = 0; i < n; ++i)
+        rem[i] = i;
+    uint32_t nout = 0;
+    while (!rem.empty()) {
+        uint32_t gpos = 0;  // tile positions of the group
+        int ng = 0;
+        uint64_t bx = 0, bz = 0;
+        const uint32_t first = nout;
+        left.clear();
+        std::vector<size_t> taken;
+        for (const size_t idx : rem) {
+            const Xform &t = x[idx];
+            if (pos_of[t.ion] < 0)
+                return hipErrorInvalidValue;
+            const uint64_t ux = 1ull << t.ion, uz = t.cion >= 0 ? (1ull << t.cion) : 0ull;
+            const uint32_t pbit = 1u << pos_of[t.ion];
+            bool ok = (ux & (bx | bz)) == 0 && (uz & bx) == 0;
+            if (ok && !(gpos & pbit)) {
+                if (ng == 2) {
+                    ok = false;
+                } else {
+                    gpos |= pbit;
+                    ++ng;
+                }
+            }
+            if (ok) {
+                taken.push_back(idx);
             } else {
-                op.oplace = (uint32_t)pow3(x[i].cion);
+                left.push_back(idx);
+                bx |= ux;
+                bz |= uz;
             }
         }
-        for (int k = 0; k < 4; ++k)
-            op.u[k] = {(R)x[i].u[2 * k], (R)x[i].u[2 * k + 1]};
+        if (ng == 1)
+            gpos |= (gpos & 1u) ? 2u : 1u;  // any other tile position
+        // pa < pb, as the kernel places the thread's digits around them
+        const uint32_t pa = (uint32_t)__builtin_ctz(gpos);
+        const uint32_t pb = (uint32_t)__builtin_ctz(gpos & (gpos - 1));
+        for (const size_t idx : taken) {
+            const Xform &t = x[idx];
+            Run3Op<R> &op = A.ops[nout++];
+            const uint32_t pos = (uint32_t)pos_of[t.ion];
+            op.place = pow3c((int)pos);
+            op.a = (uint32_t)t.a;
+            op.b = (uint32_t)t.b;
+            op.mode = t.mode;
+            op.cplace = 0;
+            op.oplace = 0;
+            op.clevel = (uint32_t)t.clevel;
+            op.inv_cplace = 0.0f;
+            const uint32_t lv = t.a == 0 ? (t.b == 1 ? 0u : 1u) : 2u;
+            op.shape = (pos == pa ? 0u : 1u) | lv << 1;
+            if (t.cion >= 0) {
+                const int cp = pos_of[t.cion];
+                if (cp < 0) {
+                    op.oplace = (uint32_t)pow3(t.cion);
+                } else if ((uint32_t)cp == pa || (uint32_t)cp == pb) {
+                    op.shape |= 8u;  // the other group ion
+                } else {
+                    op.cplace = pow3c(cp);
+                    op.inv_cplace = 1.0f / (float)op.cplace;
+                }
+            }
+            for (int k = 0; k < 4; ++k)
+                op.u[k] = {(R)t.u[2 * k], (R)t.u[2 * k + 1]};
+        }
+        A.group[A.ngroups++] = first | (nout - first) << kGroup3Count | pa << kGroup3A |
+                               pb << kGroup3B;
+        rem.swap(left);
     }
     const uint32_t grid = std::min<uint32_t>(A.ntiles, 256u * 8u);
-    hipLaunchKernelGGL((k3_tile<R>), dim3(grid), dim3(kTileBlock3), 0, s->stream, A);
+    hipLaunchKernelGGL((k3_tile<R>), dim3(grid), dim3(kTileBlock3<R>), 0, s->stream, A);
     return hipGetLastError();
 }
 
