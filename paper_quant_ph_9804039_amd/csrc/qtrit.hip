@@ -80,6 +80,10 @@ __device__ __forceinline__ uint32_t div_by(uint32_t n, uint32_t d, double inv)
 
 // What a launch does to the pairs (level a, level b) of its ion.
 enum PairMode : uint32_t { kPairMat = 0, kPairSwap = 1, kPairNegB = 2 };
+// Cheaper forms of kPairMat the fused pass recognises: a rotation pulse
+// (u00 = u11 = c real, u10 = -conj(u01): 12 flops per pair instead of 16)
+// and a diagonal (a phase pulse: 8).
+enum : uint32_t { kPairRot = 3, kPairDiag = 4 };
 
 template <typename R>
 struct RotArgs {
@@ -218,6 +222,17 @@ __device__ __forceinline__ void quantum_pairs(const Run3Op<R> &op, bool C, bool 
         } else if (op.mode == kPairNegB) {
             const bool s = !W || act;
             x[j] = {s ? -q.re : q.re, s ? -q.im : q.im};
+        } else if (op.mode == kPairRot) {
+            // [[c, v], [-conj(v), c]], v = (va, vb)
+            const R c = !W || act ? op.u[0].re : R(1);
+            const R va = !W || act ? op.u[1].re : R(0), vb = !W || act ? op.u[1].im : R(0);
+            x[i] = {c * p.re + va * q.re - vb * q.im, c * p.im + va * q.im + vb * q.re};
+            x[j] = {c * q.re - va * p.re - vb * p.im, c * q.im - va * p.im + vb * p.re};
+        } else if (op.mode == kPairDiag) {
+            const cplx<R> d0 = {!W || act ? op.u[0].re : R(1), !W || act ? op.u[0].im : R(0)};
+            const cplx<R> d1 = {!W || act ? op.u[3].re : R(1), !W || act ? op.u[3].im : R(0)};
+            x[i] = qsim::cmul(d0, p);
+            x[j] = qsim::cmul(d1, q);
         } else if (W) {
             const R one = R(1), zero = R(0);
             const cplx<R> u0 = {act ? op.u[0].re : one, act ? op.u[0].im : zero};
@@ -818,6 +833,15 @@ hipError_t launch_run(qsim3_state *s, const Xform *x, size_t n, const std::vecto
             op.a = (uint32_t)t.a;
             op.b = (uint32_t)t.b;
             op.mode = t.mode;
+            if (t.mode == kPairMat) {
+                const cplx<R> u00 = {(R)t.u[0], (R)t.u[1]}, u01 = {(R)t.u[2], (R)t.u[3]};
+                const cplx<R> u10 = {(R)t.u[4], (R)t.u[5]}, u11 = {(R)t.u[6], (R)t.u[7]};
+                if (u01.re == R(0) && u01.im == R(0) && u10.re == R(0) && u10.im == R(0))
+                    op.mode = kPairDiag;
+                else if (u00.im == R(0) && u11.im == R(0) && u00.re == u11.re &&
+                         u10.re == -u01.re && u10.im == u01.im)
+                    op.mode = kPairRot;
+            }
             op.cplace = 0;
             op.oplace = 0;
             op.clevel = (uint32_t)t.clevel;
