@@ -298,6 +298,10 @@ def bench_three_state(q, cg, np):
     eb = 8
     pair_amps = 2 * 3 ** (M3 - 1)
     amps = sum(pair_amps // (3 if p["cond_ion"] >= 0 else 1) for p in pulses)
+    # algorithmic flops: a rotation pulse updates each amplitude of a pair as
+    # c*a + v*b (2 + 6 + 2 flops), a phase pulse as one complex product (6)
+    flops = sum(pair_amps // (3 if p["cond_ion"] >= 0 else 1) * (10 if p["kind"] == 0 else 6)
+                for p in pulses)
     out = {"num_ions": M3, "amplitudes": 3 ** M3, "gates": G3, "transformations": len(pulses),
            "dtype": "c64"}
     results = {}
@@ -328,7 +332,9 @@ def bench_three_state(q, cg, np):
         else:
             # a fused pass reads and writes the whole register once
             gbps = launches * 2 * 3 ** M3 * eb / wall / 1e9
-        rec.update({"algorithmic_GBps": gbps, "hbm_frac": gbps / HBM_PEAK_GBS})
+        tflops = flops / wall / 1e12
+        rec.update({"algorithmic_GBps": gbps, "hbm_frac": gbps / HBM_PEAK_GBS,
+                    "algorithmic_TFLOPs": tflops, "alu_frac": tflops / ALU_PEAK_TFLOPS})
         out[name] = rec
     out["fused_vs_per_transformation_max_abs_diff"] = float(
         np.max(np.abs(results["fused"] - results["per_transformation"])))
