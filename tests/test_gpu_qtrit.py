@@ -200,9 +200,12 @@ def test_fused_passes_vs_oracle_and_per_transformation_path(dtype, M, seed):
     assert np.max(np.abs(out[2] - out[1])) <= TOL[dtype]
 
 
-def test_fused_conditional_transformations_inside_and_outside_the_tile():
-    """Conditions on ions inside and outside a pass's tile (M = 11 complex128:
-    a tile holds 7 of the 11 ions)."""
+@pytest.mark.parametrize("dtype", [q.QSIM_C128, q.QSIM_C64])
+def test_fused_conditional_transformations_inside_and_outside_the_tile(dtype):
+    """Conditions on ions inside and outside a pass's tile (M = 11: a tile
+    holds 7 (complex128) or 8 (complex64) of the 11 ions), on the other ion
+    of a register group, on a tile ion outside the group, and on an ion
+    outside the tile."""
     M = 11
     rng = np.random.default_rng(77)
     pulses = []
@@ -223,8 +226,9 @@ def test_fused_conditional_transformations_inside_and_outside_the_tile():
                 "theta": 0.7, "phi": -0.2 * q_} for q_ in range(M)]
     for p in spread + pulses:
         oracle.apply_pulse3(psi, M, p)
+    tol = 1e-12 if dtype == q.QSIM_C128 else 2e-5
     for mode in (0, 2):
-        with q.State3(M, q.QSIM_C128, q.make_options(exec_mode=mode)) as s:
+        with q.State3(M, dtype, q.make_options(exec_mode=mode)) as s:
             s.reset(5)
             s.apply_pulses(spread + pulses)
-            assert np.max(np.abs(s.amplitudes() - oracle.as_complex(psi))) < 1e-12
+            assert np.max(np.abs(s.amplitudes() - oracle.as_complex(psi))) < tol
