@@ -154,7 +154,11 @@ __global__ void __launch_bounds__(kBlock3) k3_init(cplx<R> *psi, uint32_t n, uin
 // other group ion), with no LDS traffic and no barrier; the tile passes
 // through LDS once per group instead of once per transformation.
 
-constexpr uint32_t kLowIons3 = 3;
+// Four low ions: a tile is runs of 81 contiguous amplitudes (648 bytes of
+// complex64); with three, the 216-byte runs straddled cache lines that
+// neighbouring tiles share, and the pass ran 5 % slower for the same number
+// of passes.
+constexpr uint32_t kLowIons3 = 4;
 template <typename R>
 constexpr int kTileIons3 = sizeof(R) == 4 ? 8 : 7;   // 3^8 x 8 B = 51 KiB, 3^7 x 16 B = 34 KiB
 template <typename R>
