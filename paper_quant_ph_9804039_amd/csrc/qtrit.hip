@@ -209,8 +209,8 @@ static_assert(sizeof(Tile3Args<float>) <= 4096 && sizeof(Tile3Args<double>) <= 4
 // W: conditioned on a tile ion outside the group, which `act` holds for this
 // thread (applied everywhere with the identity where act is false, so no
 // lane branches).
-template <typename R, int S, int LA, int LB, bool W>
-__device__ __forceinline__ void quantum_pairs(const Run3Op<R> &op, bool C, bool act, cplx<R> (&x)[9])
+template <typename R, int S, int LA, int LB, bool W, bool C>
+__device__ __forceinline__ void quantum_pairs(const Run3Op<R> &op, bool act, cplx<R> (&x)[9])
 {
 #pragma unroll
     for (int o = 0; o < 3; ++o) {
@@ -255,14 +255,21 @@ __device__ __forceinline__ void quantum_pairs(const Run3Op<R> &op, bool C, bool 
 template <typename R, bool W>
 __device__ __forceinline__ void quantum_op(const Run3Op<R> &op, bool act, cplx<R> (&x)[9])
 {
-    const bool C = (op.shape >> 3) & 1u;
-    switch (op.shape & 7u) {
-    case 0: quantum_pairs<R, 0, 0, 1, W>(op, C, act, x); break;
-    case 1: quantum_pairs<R, 1, 0, 1, W>(op, C, act, x); break;
-    case 2: quantum_pairs<R, 0, 0, 2, W>(op, C, act, x); break;
-    case 3: quantum_pairs<R, 1, 0, 2, W>(op, C, act, x); break;
-    case 4: quantum_pairs<R, 0, 1, 2, W>(op, C, act, x); break;
-    default: quantum_pairs<R, 1, 1, 2, W>(op, C, act, x); break;
+    // conditioned on the other group ion or not: separate code, so the
+    // unconditioned pairs carry no per-pair test
+    switch (op.shape & 15u) {
+    case 0: quantum_pairs<R, 0, 0, 1, W, false>(op, act, x); break;
+    case 1: quantum_pairs<R, 1, 0, 1, W, false>(op, act, x); break;
+    case 2: quantum_pairs<R, 0, 0, 2, W, false>(op, act, x); break;
+    case 3: quantum_pairs<R, 1, 0, 2, W, false>(op, act, x); break;
+    case 4: quantum_pairs<R, 0, 1, 2, W, false>(op, act, x); break;
+    case 5: quantum_pairs<R, 1, 1, 2, W, false>(op, act, x); break;
+    case 8: quantum_pairs<R, 0, 0, 1, W, true>(op, act, x); break;
+    case 9: quantum_pairs<R, 1, 0, 1, W, true>(op, act, x); break;
+    case 10: quantum_pairs<R, 0, 0, 2, W, true>(op, act, x); break;
+    case 11: quantum_pairs<R, 1, 0, 2, W, true>(op, act, x); break;
+    case 12: quantum_pairs<R, 0, 1, 2, W, true>(op, act, x); break;
+    default: quantum_pairs<R, 1, 1, 2, W, true>(op, act, x); break;
     }
 }
 
@@ -273,9 +280,12 @@ __constant__ uint32_t c_pow3[16] = {1u, 3u, 9u, 27u, 81u, 243u, 729u, 2187u, 656
 // One transformation of a group on the thread's quantum (bt: tile index of
 // its register 0).
 template <typename R>
-__device__ __forceinline__ void group_op(const Run3Op<R> &op, uint32_t base, uint32_t bt,
+__device__ __forceinline__ void group_op(const Run3Op<R> &desc, uint32_t base, uint32_t bt,
                                          cplx<R> (&x)[9])
 {
+    // the whole descriptor at once (one scalar wait), not a kernel-argument
+    // load at each use
+    const Run3Op<R> op = desc;
     if (op.oplace != 0 && (base / op.oplace) % 3u != op.clevel)
         return;  // uniform over the workgroup: the condition is off for this tile
     if (op.cplace == 0) {
