@@ -602,6 +602,11 @@ OpUse op_use(const Op &op)
     return {diag ? 0ull : t, op.cmask | op.zdep | (diag ? t : 0ull)};
 }
 
+// Lookahead of the tile-set and group choices: the next kWindow operations,
+// up to kMaxExchanges exchanges.
+constexpr size_t kWindow = 64;
+constexpr int kMaxExchanges = 4;
+
 // Reorder the operations of one fused pass, order[first, first + count), so
 // that they fall into few register groups (each group is one LDS
 // re-partition of the tile): repeatedly take, in order, every operation that
@@ -614,9 +619,17 @@ void cluster_pass(const std::vector<Op> &ops, std::vector<uint32_t> &order, size
                               order.begin() + (std::ptrdiff_t)(first + count));
     std::vector<uint32_t> left, out;
     out.reserve(count);
+    std::vector<ScanOp> w;
     while (!rem.empty()) {
-        uint64_t cur = 0, bx = 0, bz = 0;
-        int ncur = 0;
+        // the group's target bits by the same lookahead as a pass's tile set
+        w.clear();
+        for (const uint32_t idx : rem) {
+            const Op &op = ops[idx];
+            const OpUse u = op_use(op);
+            w.push_back({u.x, u.z, needs_tile_target(op) ? (1ull << op.target) : 0ull});
+        }
+        uint64_t cur = lookahead_set(w, 0, G, w.size(), kMaxExchanges), bx = 0, bz = 0;
+        int ncur = __builtin_popcountll(cur);
         left.clear();
         for (const uint32_t idx : rem) {
             const Op &op = ops[idx];
@@ -651,8 +664,6 @@ void cluster_pass(const std::vector<Op> &ops, std::vector<uint32_t> &order, size
 // random circuits at 30 qubits: 30-33 passes instead of 36-39 with sets
 // filled first come, first served, for about 3 ms of host time per 1000
 // gates).
-constexpr size_t kWindow = 64;
-constexpr int kMaxExchanges = 4;
 
 uint64_t choose_tile_set(const std::vector<Op> &ops, const std::vector<uint32_t> &rem,
                          uint64_t S0, int k, size_t cap)

@@ -149,3 +149,23 @@ def test_lookahead_tile_sets_carry_more_operations(seed, most):
     passes, _, _ = _check(M, gates, em, q.make_options(lazy_qubits=-1, renorm_period=64), period=64)
     assert len(passes) <= most
     assert all(p["n_ops"] >= 1 for p in passes)
+
+
+@pytest.mark.parametrize("seed", [30, 31, 32])
+def test_register_groups_close_to_the_target_bound(seed):
+    # A pass needs at least ceil(distinct targets / G) register groups (G = 4).
+    # Choosing each group's target bits by lookahead over the pass's
+    # operations stays within a fifth of that bound (filling the bits first
+    # come, first served was a quarter above it).
+    M = 30
+    gates = cg.random_circuit(M, 1000, seed)
+    em = oracle.Errors(sigma=1e-3, p_bitflip=1e-4, p_phaseflip=1e-4, seed=1030, trial=1)
+    passes, order, ops = _check(M, gates, em, q.make_options(lazy_qubits=-1, renorm_period=64),
+                                period=64)
+    bound = 0
+    for p in passes:
+        targets = {ops[i][2] for i in order[p["first_op"]: p["first_op"] + p["n_ops"]]
+                   if ops[i][2] is not None}
+        bound += -(-len(targets) // 4)
+    groups = sum(p["n_groups"] for p in passes)
+    assert bound <= groups <= 1.2 * bound
