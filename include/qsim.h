@@ -171,7 +171,12 @@ int qsim_destroy(qsim_state *s);
 
 /* Set the state to the basis state |basis_index> (Sec. 1.2, Fig. 1(a): one
  * amplitude 1, every other 0) and the step counter to 0; the armed error
- * model stays armed.  ERANGE if basis_index >= 2^M. */
+ * model stays armed.  ERANGE if basis_index >= 2^M.  The register memory is
+ * written by the next call that touches the state: the first fused pass of
+ * an apply call builds the basis state instead of loading the register, and
+ * every readout, qsim_set_amplitudes, qsim_synchronize and a qsim_info that
+ * asks for the device pointer write it first.  Code that reads the memory
+ * directly does so after one of those calls. */
 int qsim_reset(qsim_state *s, uint64_t basis_index);
 
 /* Apply gates[0..n_gates) in order (Sec. 2.1), each followed by the armed

@@ -93,6 +93,8 @@ struct qsim_state {
     int remap = 0;           // qubit remap: 0 automatic, 1 eager, -1 never
     uint64_t active = 0;     // touched qubits: amplitudes spread over both values
     uint64_t fixed = 0;      // the value of every untouched qubit
+    bool init_pending = false;  // reset to basis state init_index, not yet written
+    uint64_t init_index = 0;
     int tile_bits = 13;
     int low_bits = 5;
     int group_bits = 5;
@@ -1257,9 +1259,37 @@ void track_pass(const std::vector<Op> &ops, const PassPlan &p, uint64_t &act, ui
     }
 }
 
+// Write a reset that is still pending (readouts, direct access to the
+// memory).  The state's contents are unchanged by it, so const callers may
+// settle too.
+int settle(const qsim_state *cs)
+{
+    qsim_state *s = const_cast<qsim_state *>(cs);
+    if (!s->init_pending)
+        return QSIM_OK;
+    HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+    HIP_TRY(s->dtype == QSIM_C64
+                ? launch_init_basis<float>((cplx<float> *)s->psi, s->M, s->init_index, s->stream)
+                : launch_init_basis<double>((cplx<double> *)s->psi, s->M, s->init_index, s->stream),
+            "init launch");
+    s->init_pending = false;
+    return QSIM_OK;
+}
+
+#define SETTLE(st)                       \
+    do {                                 \
+        const int rc_ = settle(st);      \
+        if (rc_ != QSIM_OK)              \
+            return rc_;                  \
+    } while (0)
+
 template <typename R>
 int run_ops(qsim_state *s, std::vector<Op> &stream)
 {
+    // a reset still pending is written by the first pass when that pass is a
+    // fused one over the whole register (it builds its quanta instead of
+    // loading them), else by an initialisation pass first
+    bool gen_first = s->init_pending;
     s->stats.remaps += (uint64_t)prepare_stream(s, stream);
     std::vector<PassPlan> plan;
     std::vector<uint32_t> order;
@@ -1280,6 +1310,18 @@ int run_ops(qsim_state *s, std::vector<Op> &stream)
             if (A.nsrun > (uint32_t)kMaxRuns || A.ncrun > (uint32_t)kMaxRuns ||
                 A.mact < A.k || A.mact > (uint32_t)s->M)
                 return fail(QSIM_EDEVICE, "internal: fused pass tables out of range");
+            A.gen = 0;
+            A.gen_index = 0;
+            if (gen_first) {
+                if (A.mact == (uint32_t)s->M && A.base_or == 0) {
+                    A.gen = 1;
+                    A.gen_index = s->init_index;
+                } else {
+                    HIP_TRY(launch_init_basis<R>(psi, s->M, s->init_index, s->stream), "init launch");
+                }
+                gen_first = false;
+                s->init_pending = false;
+            }
             A.psi = psi;
             A.scale_in = scale_pending ? norm_sum + 1 : nullptr;
             A.norm_out = p.norm_after ? s->d_tile_norm : nullptr;
@@ -1301,6 +1343,11 @@ int run_ops(qsim_state *s, std::vector<Op> &stream)
                 s->stats.renorms++;
             }
         } else {
+            if (gen_first) {
+                HIP_TRY(launch_init_basis<R>(psi, s->M, s->init_index, s->stream), "init launch");
+                gen_first = false;
+                s->init_pending = false;
+            }
             if (scale_pending) {
                 Timed t0(s, 2, full);
                 HIP_TRY(launch_scale<R>(psi, s->M, norm_sum + 1, s->stream), "scale launch");
@@ -1322,6 +1369,10 @@ int run_ops(qsim_state *s, std::vector<Op> &stream)
         }
         track_pass(ops, p, act, fixed);
         s->stats.passes++;
+    }
+    if (gen_first) {  // an empty call
+        HIP_TRY(launch_init_basis<R>(psi, s->M, s->init_index, s->stream), "init launch");
+        s->init_pending = false;
     }
     if (scale_pending) {
         Timed t0(s, 2, full);
@@ -1494,6 +1545,8 @@ int slot_state_bind(qsim_state *s, int num_qubits, int dtype, void *psi)
 
 int overlap_enqueue(const qsim_state *a, const qsim_state *b, double *host_out4)
 {
+    SETTLE(a);
+    SETTLE(b);
     hipError_t e;
     if (a->dtype == QSIM_C64 && b->dtype == QSIM_C64)
         e = launch_overlap<float, float>((const cplx<float> *)a->psi, (const cplx<float> *)b->psi,
@@ -1611,13 +1664,10 @@ int qsim_reset(qsim_state *s, uint64_t basis_index)
             return fail(QSIM_EINVAL, "state is NULL");
         if (basis_index >= (1ull << s->M))
             return fail(QSIM_ERANGE, "basis index %llu >= 2^%d", (unsigned long long)basis_index, s->M);
-        HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
-        Timed t(s, 2, 0);
-        HIP_TRY(s->dtype == QSIM_C64
-                    ? launch_init_basis<float>((cplx<float> *)s->psi, s->M, basis_index, s->stream)
-                    : launch_init_basis<double>((cplx<double> *)s->psi, s->M, basis_index, s->stream),
-                "init launch");
-        t.done();
+        // written by the first pass of the next call that applies gates (or
+        // before anything reads the register), not by a pass of its own
+        s->init_pending = true;
+        s->init_index = basis_index;
         s->step = 0;
         s->active = s->lazy ? 0 : full_mask(s->M);
         s->fixed = basis_index & ~s->active;
@@ -1695,6 +1745,7 @@ int qsim_synchronize(qsim_state *s)
     return guarded(__func__, [&]() -> int {
         if (s == nullptr)
             return fail(QSIM_EINVAL, "state is NULL");
+        SETTLE(s);
         HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
         HIP_TRY(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
         return QSIM_OK;
@@ -1711,6 +1762,8 @@ int qsim_overlap(const qsim_state *a, const qsim_state *b, double out[4])
         if (a->device != b->device)
             return fail(QSIM_EINVAL, "states live on different devices");
         qsim_state *sa = const_cast<qsim_state *>(a);
+        SETTLE(a);
+        SETTLE(b);
         HIP_TRY(hipSetDevice(a->device), "hipSetDevice");
         if (a->stream != b->stream) {
             hipEvent_t ev;
@@ -1769,6 +1822,7 @@ int qsim_norm(const qsim_state *s, double *out)
             return fail(QSIM_EINVAL, "NULL argument");
         qsim_state *m = const_cast<qsim_state *>(s);
         HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+        SETTLE(s);
         Timed t(m, 2, 0);
         HIP_TRY(s->dtype == QSIM_C64
                     ? launch_norm<float>((const cplx<float> *)s->psi, s->M, s->d_partial,
@@ -1798,6 +1852,7 @@ int qsim_probs(const qsim_state *s, uint64_t qubit_mask, double *out, size_t out
             return fail(QSIM_EINVAL, "out_len %zu != 2^%d", out_len, m);
         qsim_state *ms = const_cast<qsim_state *>(s);
         HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+        SETTLE(s);
         const size_t out_bytes = out_len * sizeof(double);
         if (qubit_mask == full) {
             int rc = ensure_stage(ms, out_bytes);
@@ -1850,6 +1905,7 @@ int qsim_get_amplitudes(const qsim_state *s, uint64_t offset, uint64_t count, do
                         (unsigned long long)offset, (unsigned long long)count, s->M);
         qsim_state *ms = const_cast<qsim_state *>(s);
         HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+        SETTLE(s);
         const uint64_t chunk = std::min<uint64_t>(count, 1ull << 22);
         if (count == 0)
             return QSIM_OK;
@@ -1884,6 +1940,7 @@ int qsim_set_amplitudes(qsim_state *s, uint64_t offset, uint64_t count, const do
             if (!std::isfinite(in[i]))
                 return fail(QSIM_EINVAL, "non-finite input at %llu", (unsigned long long)i);
         HIP_TRY(hipSetDevice(s->device), "hipSetDevice");
+        SETTLE(s);
         if (count == 0)
             return QSIM_OK;
         const uint64_t chunk = std::min<uint64_t>(count, 1ull << 22);
@@ -2009,7 +2066,10 @@ int qsim_info(const qsim_state *s, int *num_qubits, int *dtype, uint64_t *step, 
         if (num_qubits) *num_qubits = s->M;
         if (dtype) *dtype = s->dtype;
         if (step) *step = s->step;
-        if (device_ptr) *device_ptr = s->psi;
+        if (device_ptr) {
+            SETTLE(s);  // whoever reads the memory sees the state
+            *device_ptr = s->psi;
+        }
         if (bytes) *bytes = s->bytes;
         return QSIM_OK;
     });

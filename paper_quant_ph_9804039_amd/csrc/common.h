@@ -203,6 +203,8 @@ struct TileArgs {
     uint32_t group[kMaxGroups];        // see group_first / group_count / group_bit
     R phase[2];                        // global phase of the pass's uncontrolled diagonals
     uint32_t use_phase;                // phase != 1
+    uint32_t gen;                      // the register is basis state gen_index: the first
+    uint64_t gen_index;                //   group builds its quanta instead of loading them
     TileOp<R> ops[kPassOps<R>];
 };
 

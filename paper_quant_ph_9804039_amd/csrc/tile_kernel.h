@@ -543,7 +543,16 @@ k_tile(const TileArgs<R> A)
     for (; tile_id < t_end; ++tile_id) {
         const uint64_t base = ebits | A.base_or;
         ebits = ((ebits | ~E) + 1u) & E;
-        load_quantum<R, G>(A.psi + (base | rel0), o0, pair00, x);
+        if (A.gen != 0) {
+            // a register just reset to a basis state: its one nonzero amplitude
+            // is written here instead of by a pass of its own
+            const uint64_t rel = base | rel0;
+#pragma unroll
+            for (int r = 0; r < (1 << G); ++r)
+                x[r] = {R(rel + greg<G>(o0, r) == A.gen_index ? 1 : 0), R(0)};
+        } else {
+            load_quantum<R, G>(A.psi + (base | rel0), o0, pair00, x);
+        }
         if (scaled) {
 #pragma unroll
             for (int r = 0; r < (1 << G); ++r) {
