@@ -26,18 +26,20 @@ struct ScanOp {
     uint64_t x, z, t;
 };
 
-// Operations of w the scan takes with the fixed set S (at most cap).
+// Operations of w the scan takes with the fixed set S (at most cap).  The
+// lookahead calls this a few thousand times per pass, so it is written
+// without branches.
 inline size_t scan_count(const std::vector<ScanOp> &w, uint64_t S, size_t cap)
 {
     uint64_t bx = 0, bz = 0;
     size_t n = 0;
     for (const ScanOp &u : w) {
-        if (n < cap && (u.x & (bx | bz)) == 0 && (u.z & bx) == 0 && (u.t & ~S) == 0) {
-            ++n;
-        } else {
-            bx |= u.x;
-            bz |= u.z;
-        }
+        const uint64_t blocked = (u.x & (bx | bz)) | (u.z & bx) | (u.t & ~S);
+        const uint64_t take = (blocked == 0) & (n < cap);
+        const uint64_t keep = take - 1;  // all ones when the operation stays behind
+        n += take;
+        bx |= u.x & keep;
+        bz |= u.z & keep;
     }
     return n;
 }
