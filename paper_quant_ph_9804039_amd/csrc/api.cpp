@@ -664,8 +664,8 @@ void cluster_pass(const std::vector<Op> &ops, std::vector<uint32_t> &order, size
 // Tile set of the next fused pass in reorder mode, by lookahead over the
 // next kWindow operations with up to kMaxExchanges exchanges (the 1000-gate
 // random circuits at 30 qubits: 30-33 passes instead of 36-39 with sets
-// filled first come, first served, for about 3 ms of host time per 1000
-// gates).
+// filled first come, first served; with the group lookahead about 5 ms of
+// host time per 1000 gates).
 
 uint64_t choose_tile_set(const std::vector<Op> &ops, const std::vector<uint32_t> &rem,
                          uint64_t S0, int k, size_t cap)
