@@ -175,8 +175,8 @@ int qsim_destroy(qsim_state *s);
  * written by the next call that touches the state: the first fused pass of
  * an apply call builds the basis state instead of loading the register, and
  * every readout, qsim_set_amplitudes, qsim_synchronize and a qsim_info that
- * asks for the device pointer write it first.  Code that reads the memory
- * directly does so after one of those calls. */
+ * asks for the device pointer write it first (on the state's stream).  Code
+ * that reads the memory directly calls qsim_synchronize first. */
 int qsim_reset(qsim_state *s, uint64_t basis_index);
 
 /* Apply gates[0..n_gates) in order (Sec. 2.1), each followed by the armed

@@ -97,3 +97,20 @@ def test_reset_twice_keeps_the_last_index(dtype):
         s.reset(77)
         s.apply(g)
         assert np.max(np.abs(s.amplitudes() - ref)) <= TOL[dtype]
+
+
+def test_direct_readers_see_the_reset_state_after_synchronize():
+    # a reader of the device memory (here the allocation-free overlap, which
+    # takes raw pointers) calls synchronize first, which writes a pending
+    # reset and waits for it
+    M, k = 12, 1234
+    with scrambled(M, q.QSIM_C64) as a, scrambled(M, q.QSIM_C64) as b:
+        a.reset(k)
+        a.synchronize()
+        b.synchronize()
+        ia, ib = a.info(), b.info()
+        ov, na, _ = q.qsim_overlap_noalloc(ia["device_ptr"], ia["dtype"], ib["device_ptr"],
+                                           ib["dtype"], M)
+        bv = b.amplitudes()
+        assert na == 1.0
+        assert abs(ov - bv[k]) <= 1e-7
