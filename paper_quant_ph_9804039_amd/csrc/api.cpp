@@ -680,118 +680,152 @@ uint64_t choose_tile_set(const std::vector<Op> &ops, const std::vector<uint32_t>
     return lookahead_set(w, S0, k, cap, kMaxExchanges);
 }
 
-// Partition ops[lo, hi) into fused passes, appending the operations to
-// `order` pass by pass.  A pass starts with the low qubits in its tile set
-// (plus, in reorder mode, the qubits choose_tile_set picks) and scans the
-// operations not yet placed, in stream order: it takes an operation when the
-// operation commutes with every earlier one still left behind and its target
-// is in the tile set or the set has room for it (diagonal operations without
-// controls never constrain the set).  In-order mode stops the scan at the
-// first operation it cannot take instead, so passes are runs of the stream.
-// Every pass takes at least one operation: the first one left commutes with
-// nothing earlier, and either the set has room for its target or the set was
-// chosen to take something from the window.
-void schedule_fused(const qsim_state *s, const std::vector<Op> &ops, size_t lo, size_t hi, int k,
-                    int G, bool reorder, std::vector<uint32_t> &order,
-                    std::vector<PassPlan> &plan)
+// One fused pass taken from the operations `rem` not yet placed (stream
+// indices, in stream order; what the pass leaves behind stays in `rem`),
+// appending its operations to `order`.  A pass starts with the low qubits in
+// its tile set (plus, in reorder mode, the qubits choose_tile_set picks) and
+// scans the operations not yet placed, in stream order: it takes an
+// operation when the operation commutes with every earlier one still left
+// behind and its target is in the tile set or the set has room for it
+// (diagonal operations without controls never constrain the set).  In-order
+// mode stops the scan at the first operation it cannot take instead, so
+// passes are runs of the stream.  Every pass takes at least one operation:
+// the first one left commutes with nothing earlier, and either the set has
+// room for its target or the set was chosen to take something from the
+// window.
+PassPlan fused_pass(const qsim_state *s, const std::vector<Op> &ops, std::vector<uint32_t> &rem,
+                    std::vector<uint32_t> &left, int k, int G, bool reorder,
+                    std::vector<uint32_t> &order)
 {
     const int low = std::min(s->low_bits, k);
     const size_t cap = s->dtype == QSIM_C64 ? (size_t)kPassOps<float> : (size_t)kPassOps<double>;
-    std::vector<uint32_t> rem, left;
-    for (size_t i = lo; i < hi; ++i)
-        rem.push_back((uint32_t)i);
-    while (!rem.empty()) {
-        uint64_t S = (low >= 64) ? ~0ull : ((1ull << low) - 1);
-        if (reorder)
-            S = choose_tile_set(ops, rem, S, k, cap);
-        int size = __builtin_popcountll(S);
-        uint64_t bx = 0, bz = 0;  // qubits held by operations left behind
-        const size_t first = order.size();
-        size_t taken = 0;
-        left.clear();
-        for (size_t r = 0; r < rem.size(); ++r) {
-            const Op &op = ops[rem[r]];
-            const OpUse u = op_use(op);
-            bool ok = taken < cap && (u.x & (bx | bz)) == 0 && (u.z & bx) == 0;
-            if (ok && needs_tile_target(op)) {
-                const uint64_t tb = 1ull << op.target;
-                if (!(S & tb)) {
-                    if (size == k) {
-                        ok = false;
-                    } else {
-                        S |= tb;
-                        ++size;
-                    }
+    uint64_t S = (low >= 64) ? ~0ull : ((1ull << low) - 1);
+    if (reorder)
+        S = choose_tile_set(ops, rem, S, k, cap);
+    int size = __builtin_popcountll(S);
+    uint64_t bx = 0, bz = 0;  // qubits held by operations left behind
+    const size_t first = order.size();
+    size_t taken = 0;
+    left.clear();
+    for (size_t r = 0; r < rem.size(); ++r) {
+        const Op &op = ops[rem[r]];
+        const OpUse u = op_use(op);
+        bool ok = taken < cap && (u.x & (bx | bz)) == 0 && (u.z & bx) == 0;
+        if (ok && needs_tile_target(op)) {
+            const uint64_t tb = 1ull << op.target;
+            if (!(S & tb)) {
+                if (size == k) {
+                    ok = false;
+                } else {
+                    S |= tb;
+                    ++size;
                 }
             }
-            if (ok) {
-                order.push_back(rem[r]);
-                ++taken;
-                continue;
-            }
-            if (!reorder || taken == cap) {
-                left.insert(left.end(), rem.begin() + (std::ptrdiff_t)r, rem.end());
-                break;
-            }
-            left.push_back(rem[r]);
-            bx |= u.x;
-            bz |= u.z;
         }
-        plan.push_back({true, first, taken, false});
-        if (reorder)
-            cluster_pass(ops, order, first, taken, G);
-        rem.swap(left);
+        if (ok) {
+            order.push_back(rem[r]);
+            ++taken;
+            continue;
+        }
+        if (!reorder || taken == cap) {
+            left.insert(left.end(), rem.begin() + (std::ptrdiff_t)r, rem.end());
+            break;
+        }
+        left.push_back(rem[r]);
+        bx |= u.x;
+        bz |= u.z;
     }
+    if (reorder)
+        cluster_pass(ops, order, first, taken, G);
+    rem.swap(left);
+    return {true, first, taken, false};
 }
 
 // Partition the operation stream into passes and fix the order in which the
-// operations run (order[i] = stream index of the i-th operation to run).  An
-// operation a fused pass cannot carry gets a pass of its own, and no
-// operation moves across it.  Plain mode, and registers too small for a
-// tile (M < 9), run one pass per operation in stream order.
+// operations run (order[i] = stream index of the i-th operation to run), one
+// pass at a time, so that a caller can launch each pass while the next one is
+// planned.  An operation a fused pass cannot carry gets a pass of its own,
+// and no operation moves across it.  Plain mode, and registers too small for
+// a tile (M < 9), run one pass per operation in stream order.
 //
 // Renormalisation is a scaling of the whole state, which commutes with every
 // operation, so it does not pin the order: the norm is taken after the first
 // pass by which every operation up to a renormalisation boundary has run
 // (several boundaries may share one), and the next pass applies the scale.
+class PassScheduler {
+public:
+    PassScheduler(const qsim_state *s, const std::vector<Op> &ops)
+        : s_(s), ops_(ops), n_(ops.size()), ran_(ops.size(), false)
+    {
+        plain_ = s->exec_mode == 1 || !tile_shape(s, k_, G_);
+        reorder_ = s->exec_mode == 0;
+        if (!plain_)
+            open_segment(0);
+    }
+
+    // The next pass (its operations appended to order); false when done.
+    bool next(std::vector<uint32_t> &order, PassPlan &p)
+    {
+        if (plain_) {
+            if (i_ >= n_)
+                return false;
+            order.push_back((uint32_t)i_);
+            p = {false, order.size() - 1, 1, false};
+            ++i_;
+        } else if (!rem_.empty()) {
+            p = fused_pass(s_, ops_, rem_, left_, k_, G_, reorder_, order);
+        } else if (seg_end_ < n_) {
+            // the operation that ended the segment, then the next segment
+            order.push_back((uint32_t)seg_end_);
+            p = {false, order.size() - 1, 1, false};
+            open_segment(seg_end_ + 1);
+        } else {
+            return false;
+        }
+        for (size_t i = p.first; i < p.first + p.count; ++i)
+            ran_[order[i]] = true;
+        while (prefix_ < n_ && ran_[prefix_])
+            ++prefix_;
+        for (; next_ < prefix_; ++next_)
+            if (ops_[next_].norm_mark)
+                p.norm_after = true;
+        return true;
+    }
+
+private:
+    // operations [lo, first operation a fused pass cannot carry) become rem_
+    void open_segment(size_t lo)
+    {
+        seg_end_ = lo;
+        while (seg_end_ < n_ && fusable(ops_[seg_end_]))
+            ++seg_end_;
+        rem_.clear();
+        for (size_t i = lo; i < seg_end_; ++i)
+            rem_.push_back((uint32_t)i);
+    }
+
+    const qsim_state *s_;
+    const std::vector<Op> &ops_;
+    size_t n_;
+    int k_ = 0, G_ = 0;
+    bool plain_ = true, reorder_ = false;
+    size_t i_ = 0;                   // plain mode: next operation
+    size_t seg_end_ = 0;             // fused mode: end of the current segment
+    std::vector<uint32_t> rem_, left_;
+    std::vector<bool> ran_;
+    size_t prefix_ = 0;  // every stream index below it has run
+    size_t next_ = 0;    // next operation to check for a boundary
+};
+
 void schedule(const qsim_state *s, const std::vector<Op> &ops, std::vector<uint32_t> &order,
               std::vector<PassPlan> &plan)
 {
-    const size_t n = ops.size();
     order.clear();
-    order.reserve(n);
-    int k, G;
-    if (s->exec_mode == 1 || !tile_shape(s, k, G)) {
-        for (size_t i = 0; i < n; ++i) {
-            order.push_back((uint32_t)i);
-            plan.push_back({false, i, 1, false});
-        }
-    } else {
-        const bool reorder = s->exec_mode == 0;
-        size_t lo = 0;
-        for (size_t i = 0; i < n; ++i) {
-            if (!fusable(ops[i])) {
-                schedule_fused(s, ops, lo, i, k, G, reorder, order, plan);
-                order.push_back((uint32_t)i);
-                plan.push_back({false, order.size() - 1, 1, false});
-                lo = i + 1;
-            }
-        }
-        schedule_fused(s, ops, lo, n, k, G, reorder, order, plan);
-    }
-    // renormalisation points
-    std::vector<bool> ran(n, false);
-    size_t prefix = 0;  // every stream index below it has run
-    size_t next = 0;    // next operation to check for a boundary
-    for (PassPlan &p : plan) {
-        for (size_t i = p.first; i < p.first + p.count; ++i)
-            ran[order[i]] = true;
-        while (prefix < n && ran[prefix])
-            ++prefix;
-        for (; next < prefix; ++next)
-            if (ops[next].norm_mark)
-                p.norm_after = true;
-    }
+    order.reserve(ops.size());
+    PassScheduler sched(s, ops);
+    PassPlan p;
+    while (sched.next(order, p))
+        plan.push_back(p);
 }
 
 // Runs of consecutive qubits in `mask` (below qubit M).
@@ -1291,18 +1325,22 @@ int run_ops(qsim_state *s, std::vector<Op> &stream)
     // loading them), else by an initialisation pass first
     bool gen_first = s->init_pending;
     s->stats.remaps += (uint64_t)prepare_stream(s, stream);
-    std::vector<PassPlan> plan;
+    // passes are planned one at a time and launched at once, so the host
+    // plans the next pass while the device runs the previous ones
     std::vector<uint32_t> order;
-    schedule(s, stream, order, plan);
-    std::vector<Op> ops(order.size());
-    for (size_t i = 0; i < order.size(); ++i)
-        ops[i] = stream[order[i]];
+    order.reserve(stream.size());
+    std::vector<Op> ops;
+    ops.reserve(stream.size());
+    PassScheduler sched(s, stream);
+    PassPlan p;
     cplx<R> *psi = reinterpret_cast<cplx<R> *>(s->psi);
     const double full = 2.0 * (double)(1ull << s->M) * (double)elem_bytes(s->dtype);
     bool scale_pending = false;
     double *norm_sum = s->d_scalars + 4;   // [4] = sum, [5] = 1/sqrt(sum)
     uint64_t act = s->active, fixed = s->fixed;
-    for (const PassPlan &p : plan) {
+    while (sched.next(order, p)) {
+        for (size_t i = ops.size(); i < order.size(); ++i)
+            ops.push_back(stream[order[i]]);
         if (p.fused) {
             TileArgs<R> A;
             int G = 0;
